@@ -1,0 +1,182 @@
+/*
+ * ig_oracle.h -- CPU oracle for instruction-graph generation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, sequential reference
+ * against which the HIP implementation is checked.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product library never does.  It shares no code and no header with the
+ * product (include/ig.h): the record layouts below are written out again on
+ * purpose so that both sides can be compared field by field.
+ *
+ * The oracle follows the paper's description of instruction-graph generation
+ * (Sec. 3: work assignment 3.1, allocation 3.2, coherence 3.3, horizons and
+ * epochs 3.5; Sec. 4.3 scheduler lookahead; Sec. 4.4 debug checks) on a
+ * flattened cluster of integer-id devices.  Every place the paper leaves open
+ * is settled by a documented reading; those readings are the definition of
+ * parity.
+ */
+#ifndef IG_ORACLE_H
+#define IG_ORACLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define IGO_OK 0
+#define IGO_W_UNINIT_READ 1
+#define IGO_E_INVALID (-1)
+#define IGO_E_OVERLAPPING_WRITE (-2)
+#define IGO_E_CAPACITY (-3)
+
+/* instruction kinds (Table 1 subset) */
+#define IGO_ALLOC 1
+#define IGO_COPY 2
+#define IGO_FREE 3
+#define IGO_KERNEL 4
+#define IGO_HORIZON 5
+#define IGO_EPOCH 6
+
+/* instruction flags */
+#define IGO_F_RESIZE 1
+#define IGO_F_INTER_NODE 2
+
+/* edge kind bits */
+#define IGO_DEP_TRUE 1
+#define IGO_DEP_ANTI 2
+#define IGO_DEP_OUTPUT 4
+#define IGO_DEP_LIFETIME 8
+#define IGO_DEP_SYNC 16
+
+/* access modes, mappers, init */
+#define IGO_READ 1
+#define IGO_WRITE 2
+#define IGO_READ_WRITE 3
+#define IGO_MAP_ONE_TO_ONE 0
+#define IGO_MAP_NEIGHBORHOOD 1
+#define IGO_MAP_ALL 2
+#define IGO_MAP_SLICE 3
+#define IGO_MAP_FIXED 4
+#define IGO_INIT_NONE 0
+#define IGO_INIT_HOST 1
+
+#define IGO_MAX_ACCESS 8
+#define IGO_NONE32 0xFFFFFFFFu
+#define IGO_NONE16 0xFFFFu
+
+typedef struct igo_box {
+    int64_t min[3];
+    int64_t max[3];
+} igo_box;
+
+typedef struct igo_access {
+    uint32_t buffer;
+    uint8_t mode;
+    uint8_t mapper;
+    uint8_t slice_dim;
+    uint8_t pad;
+    int64_t radius[3];
+    igo_box fixed;
+} igo_access;
+
+typedef struct igo_task_desc {
+    uint32_t dims;
+    uint32_t n_access;
+    igo_box box;
+    igo_access access[IGO_MAX_ACCESS];
+} igo_task_desc;
+
+typedef struct igo_context_desc {
+    uint32_t nodes;
+    uint32_t devices_per_node;
+    uint32_t chunks;          /* 0: nodes * devices_per_node */
+    uint32_t horizon_step;    /* 0: 4 */
+    uint32_t lookahead;       /* 0 off, 1 on */
+    uint32_t flush_horizons;  /* 0: 2 */
+    uint32_t queue_cap;       /* 0: unbounded */
+    uint32_t pad;
+} igo_context_desc;
+
+typedef struct igo_instruction {
+    uint64_t id;
+    uint8_t kind;
+    uint8_t flags;
+    uint16_t mem;
+    uint16_t src_mem;
+    uint16_t pad0;
+    uint32_t task;
+    uint32_t chunk;
+    uint32_t buffer;
+    uint32_t pad1;
+    uint64_t alloc;
+    uint64_t src_alloc;
+    igo_box box;
+} igo_instruction; /* 96 bytes */
+
+typedef struct igo_binding {
+    uint64_t instr;
+    uint32_t access;
+    uint32_t pad;
+    uint64_t alloc;
+} igo_binding; /* 24 bytes */
+
+typedef struct igo_edge {
+    uint64_t from;
+    uint64_t to;
+    uint32_t kinds;
+    uint32_t pad;
+} igo_edge; /* 24 bytes */
+
+typedef struct igo_stats {
+    uint64_t n_instructions;
+    uint64_t n_bindings;
+    uint64_t n_edges;
+    uint64_t per_kind[8];      /* index = instruction kind */
+    uint64_t per_dep[5];       /* edges carrying TRUE, ANTI, OUTPUT, LIFETIME, SYNC */
+    uint64_t resizes;          /* allocations replaced by a larger one */
+    uint64_t warnings;         /* tasks with an uninitialised read */
+    uint64_t tasks_submitted;
+    uint64_t tasks_rejected;
+    uint64_t digest_instructions;
+    uint64_t digest_bindings;
+    uint64_t digest_edges;
+} igo_stats;
+
+typedef struct igo_context igo_context;
+
+int32_t igo_context_create(const igo_context_desc* desc, igo_context** out);
+int32_t igo_context_destroy(igo_context* ctx);
+int32_t igo_buffer_create(igo_context* ctx, uint32_t dims, const int64_t extent[3],
+                          uint32_t elem_size, uint32_t init, uint32_t* out_buffer);
+int32_t igo_buffer_destroy(igo_context* ctx, uint32_t buffer);
+int32_t igo_submit_task(igo_context* ctx, const igo_task_desc* task, uint64_t* out_task);
+int32_t igo_epoch(igo_context* ctx);
+int32_t igo_shutdown(igo_context* ctx);
+int32_t igo_flush_window(igo_context* ctx);
+int32_t igo_counts(igo_context* ctx, uint64_t* n_instr, uint64_t* n_bind, uint64_t* n_edge,
+                   uint64_t* n_tasks);
+int32_t igo_fetch_instructions(igo_context* ctx, igo_instruction* dst, size_t cap, size_t* n_out);
+int32_t igo_fetch_bindings(igo_context* ctx, igo_binding* dst, size_t cap, size_t* n_out);
+int32_t igo_fetch_edges(igo_context* ctx, igo_edge* dst, size_t cap, size_t* n_out);
+int32_t igo_fetch_task_status(igo_context* ctx, int32_t* dst, size_t cap, size_t* n_out);
+int32_t igo_stats_get(igo_context* ctx, igo_stats* out);
+
+/* box-set primitives, exported so that tests can pin them against brute force */
+size_t igo_box_subtract(const igo_box* a, const igo_box* b, igo_box* out /* >= 6 */);
+int32_t igo_box_merges(const igo_box* a, const igo_box* b);
+size_t igo_canonical(const igo_box* in, size_t n, igo_box* out, size_t cap);
+size_t igo_merge_fixpoint(const igo_box* in, size_t n, igo_box* out, size_t cap);
+/* chunk split and range mapping, exported for the same reason */
+int32_t igo_split(uint32_t nodes, uint32_t devices, uint32_t chunks, const igo_box* task,
+                  igo_box* out_chunks /* chunks */);
+int32_t igo_map(const igo_access* acc, uint32_t task_dims, const igo_box* chunk,
+                uint32_t buf_dims, const int64_t extent[3], igo_box* out);
+uint64_t igo_digest(const uint64_t* words, size_t n_records, size_t words_per_record);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
