@@ -1,0 +1,273 @@
+/*
+ * ig.h -- C ABI of the MI355X instruction-graph generator (libig).
+ *
+ * Instruction-graph (IDAG) generation after Knorr, Salzmann, Thoman and
+ * Fahringer, "Concurrent Scheduling of High-Level Parallel Programs on
+ * Multi-GPU Systems" (arXiv 2503.10516): a stream of data-parallel tasks with
+ * range-mapped buffer accesses is split over a simulated cluster of
+ * integer-id devices (Sec. 3.1) and compiled into allocations and resizes
+ * (Sec. 3.2), coherence copies with producer and consumer split (Sec. 3.3),
+ * device kernels, horizons and epochs (Sec. 3.5, Table 1), with true, anti,
+ * output, allocation-lifetime and synchronisation edges (legend of the IDAG
+ * figure, Sec. 3.6), under the scheduler lookahead of Sec. 4.3 and the debug
+ * checks of Sec. 4.4.
+ *
+ * All analysis runs in HIP kernels on one gfx950 GPU, one workgroup per
+ * stream; the host side only validates arguments, records commands and moves
+ * records.  Nothing here is executed on the simulated devices.
+ *
+ * Conventions
+ *   - Every entry point returns an ig_status: 0 = IG_OK, 1 = IG_W_UNINIT_READ
+ *     (only as a per-task status), negative = error.  An error leaves the
+ *     context unchanged.
+ *   - Device memory: the caller may hand in an arena (device pointer + size,
+ *     e.g. a torch tensor) that must outlive the context; with arena == NULL
+ *     the library allocates (and frees) its own.  ig_arena_bytes() gives the
+ *     size a descriptor needs.  The stream (hipStream_t, may be NULL = the
+ *     default stream) is the caller's; all work of a context is ordered on it.
+ *   - Descriptors are copied; the caller may free them on return.
+ *   - Threading: one host thread per context at a time; contexts are
+ *     independent.  Ids (instructions, allocations, tasks) are per context,
+ *     so a stream's output is the same alone and batched with others.
+ *   - Submission is asynchronous: ig_submit_task validates and records; the
+ *     analysis of everything recorded runs at ig_flush_window (asynchronously
+ *     on the stream) and its per-task status (0, IG_W_UNINIT_READ or
+ *     IG_E_OVERLAPPING_WRITE) is read with ig_fetch_task_status after
+ *     ig_sync.
+ */
+#ifndef IG_H
+#define IG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ig_status;
+
+#define IG_OK 0
+#define IG_W_UNINIT_READ 1           /* Sec. 4.4: read of uninitialised data (task accepted) */
+#define IG_E_INVALID (-1)            /* bad argument, unknown buffer, mapper/dimension mismatch */
+#define IG_E_OVERLAPPING_WRITE (-2)  /* Sec. 4.4: chunks of one task write overlapping regions */
+#define IG_E_CAPACITY (-3)           /* a device-side table or the arena is too small */
+#define IG_E_DEVICE (-4)             /* a HIP runtime error */
+#define IG_E_BUSY (-5)               /* serving admission: no free slot */
+
+/* instruction kinds (Table 1: the subset on the hot path) */
+#define IG_ALLOC 1
+#define IG_COPY 2
+#define IG_FREE 3
+#define IG_KERNEL 4
+#define IG_HORIZON 5
+#define IG_EPOCH 6
+
+/* instruction flags */
+#define IG_F_RESIZE 1      /* copy of a resize chain (Sec. 3.2) */
+#define IG_F_INTER_NODE 2  /* copy between devices of different nodes */
+
+/* dependency kinds, a bit set per edge */
+#define IG_DEP_TRUE 1
+#define IG_DEP_ANTI 2
+#define IG_DEP_OUTPUT 4
+#define IG_DEP_LIFETIME 8
+#define IG_DEP_SYNC 16
+
+/* access modes (bit set), range mappers, buffer initialisation */
+#define IG_READ 1
+#define IG_WRITE 2
+#define IG_READ_WRITE 3
+#define IG_MAP_ONE_TO_ONE 0
+#define IG_MAP_NEIGHBORHOOD 1
+#define IG_MAP_ALL 2
+#define IG_MAP_SLICE 3
+#define IG_MAP_FIXED 4
+#define IG_INIT_NONE 0
+#define IG_INIT_HOST 1
+
+#define IG_MAX_ACCESS 8
+#define IG_MAX_BUFFERS 64
+#define IG_MAX_DEVICES 254
+#define IG_NONE32 0xFFFFFFFFu
+#define IG_NONE16 0xFFFFu
+
+/* A half-open box [min, max) in up to three dimensions; unused dimensions
+ * are [0, 1). */
+typedef struct ig_box {
+    int64_t min[3];
+    int64_t max[3];
+} ig_box;
+
+/* One accessor (Sec. 2.1): buffer, mode and range mapper.
+ *   one_to_one   region = chunk box
+ *   neighborhood region = chunk box grown by radius[d] on both sides
+ *   all          region = whole buffer
+ *   slice        region = chunk box widened to the buffer in slice_dim
+ *   fixed        region = `fixed`
+ * Every region is clipped to the buffer.  one_to_one, neighborhood and slice
+ * require task dims == buffer dims. */
+typedef struct ig_access {
+    uint32_t buffer;
+    uint8_t mode;
+    uint8_t mapper;
+    uint8_t slice_dim;
+    uint8_t pad;
+    int64_t radius[3];
+    ig_box fixed;
+} ig_access;
+
+/* A task (one command group, one kernel): its index box and accessors. */
+typedef struct ig_task_desc {
+    uint32_t dims;
+    uint32_t n_access;
+    ig_box box;
+    ig_access access[IG_MAX_ACCESS];
+} ig_task_desc;
+
+typedef struct ig_context_desc {
+    uint32_t nodes;             /* simulated nodes, >= 1 */
+    uint32_t devices_per_node;  /* devices per node, nodes*devices <= 254 */
+    uint32_t chunks;            /* chunks per task, a multiple of nodes*devices (0: one per device) */
+    uint32_t horizon_step;      /* accepted tasks between horizons (0: 4) */
+    uint32_t lookahead;         /* Sec. 4.3 command queue: 0 off, 1 on */
+    uint32_t flush_horizons;    /* horizons after the last allocating command before a flush (0: 2) */
+    uint32_t queue_cap;         /* flush when the queue holds this many commands (0: unbounded) */
+    uint32_t threads;           /* workgroup size of this stream's analysis (0: 256); tuning only */
+    uint64_t cap_commands;      /* recorded commands (0: 65536) */
+    uint64_t cap_instructions;  /* output instructions (0: 1<<22) */
+    uint64_t cap_edges;         /* output edges (0: 4 * cap_instructions) */
+    uint64_t cap_state_words;   /* 32-bit words for region maps and grids (0: 1<<24) */
+    uint64_t cap_unit;          /* instructions/edges staged per compiled command (0: 1<<20) */
+    void* arena;                /* caller-owned device memory, or NULL */
+    uint64_t arena_bytes;
+    void* stream;               /* hipStream_t, or NULL */
+} ig_context_desc;
+
+/* Output records.  Ids are per context.  For COPY, box is in buffer
+ * coordinates; KERNEL: the chunk's index box; ALLOC/FREE: the allocation's
+ * box; HORIZON/EPOCH: empty.  Unused ids are IG_NONE32 / IG_NONE16, unused
+ * allocation ids 0. */
+typedef struct ig_instruction {
+    uint64_t id;
+    uint8_t kind;
+    uint8_t flags;
+    uint16_t mem;
+    uint16_t src_mem;
+    uint16_t pad0;
+    uint32_t task;
+    uint32_t chunk;
+    uint32_t buffer;
+    uint32_t pad1;
+    uint64_t alloc;
+    uint64_t src_alloc;
+    ig_box box;
+} ig_instruction; /* 96 bytes */
+
+/* Which allocation backs access `access` of KERNEL `instr` (0: empty region). */
+typedef struct ig_binding {
+    uint64_t instr;
+    uint32_t access;
+    uint32_t pad;
+    uint64_t alloc;
+} ig_binding; /* 24 bytes */
+
+typedef struct ig_edge {
+    uint64_t from;
+    uint64_t to;
+    uint32_t kinds; /* IG_DEP_* bit set */
+    uint32_t pad;
+} ig_edge; /* 24 bytes */
+
+typedef struct ig_stats {
+    uint64_t n_instructions;
+    uint64_t n_bindings;
+    uint64_t n_edges;
+    uint64_t per_kind[8];
+    uint64_t per_dep[5];
+    uint64_t resizes;
+    uint64_t warnings;
+    uint64_t tasks_submitted;
+    uint64_t tasks_rejected;
+    uint64_t digest_instructions;
+    uint64_t digest_bindings;
+    uint64_t digest_edges;
+    uint64_t commands_analysed;
+    uint64_t launches;
+} ig_stats;
+
+typedef struct ig_context ig_context;
+
+/* Device memory a descriptor needs (arena size).  Errors: IG_E_INVALID. */
+ig_status ig_arena_bytes(const ig_context_desc* desc, uint64_t* bytes);
+
+/* Create a context: validates the cluster shape, prepares device state and
+ * records the initial epoch I0.  Errors: IG_E_INVALID, IG_E_CAPACITY (arena
+ * too small), IG_E_DEVICE. */
+ig_status ig_context_create(const ig_context_desc* desc, ig_context** out);
+
+/* Destroy: waits for outstanding work; frees library-owned memory. */
+ig_status ig_context_destroy(ig_context* ctx);
+
+/* Record a buffer (ids 0, 1, ... in creation order).  IG_INIT_HOST buffers
+ * are up to date in user memory M0 (Sec. 3.2).  Errors: IG_E_INVALID,
+ * IG_E_CAPACITY (more than IG_MAX_BUFFERS). */
+ig_status ig_buffer_create(ig_context* ctx, uint32_t dims, const int64_t extent[3], uint32_t elem_size,
+                           uint32_t init, uint32_t* out_buffer);
+
+/* Record the destruction of a buffer: flushes the command queue, then frees
+ * its device allocations (Sec. 3.2).  Errors: IG_E_INVALID. */
+ig_status ig_buffer_destroy(ig_context* ctx, uint32_t buffer);
+
+/* Record one task; *out_task receives its id.  Structural errors
+ * (IG_E_INVALID, IG_E_CAPACITY) are returned here; the Sec. 4.4 outcome is
+ * the task's status after analysis. */
+ig_status ig_submit_task(ig_context* ctx, const ig_task_desc* task, uint64_t* out_task);
+
+/* Record n tasks at once (ids out_first, out_first+1, ...).  Stops at the
+ * first invalid descriptor, recording the ones before it. */
+ig_status ig_submit_tasks(ig_context* ctx, const ig_task_desc* tasks, size_t n, uint64_t* out_first);
+
+/* Record a user epoch: flush the queue, then synchronise (Table 1). */
+ig_status ig_epoch(ig_context* ctx);
+
+/* Record shutdown: destroy every remaining buffer, then the final epoch.
+ * No command may follow. */
+ig_status ig_shutdown(ig_context* ctx);
+
+/* Analyse everything recorded so far (asynchronously on the stream).  Does
+ * not force a lookahead flush: output never depends on timing. */
+ig_status ig_flush_window(ig_context* ctx);
+
+/* Analyse the pending windows of n contexts in ONE launch (one workgroup
+ * per context; all must use the same `threads`).  stream: NULL = the first
+ * context's stream. */
+ig_status ig_batch_flush(ig_context* const* ctxs, size_t n, void* stream);
+
+/* Wait for the context's outstanding work; reports IG_E_CAPACITY or
+ * IG_E_DEVICE raised during analysis. */
+ig_status ig_sync(ig_context* ctx);
+
+/* Forget all analysis results (the recorded commands stay); the next flush
+ * re-analyses the stream from the start.  Used to re-run a recorded stream. */
+ig_status ig_rewind(ig_context* ctx);
+
+/* Counts of records produced so far (after ig_sync). */
+ig_status ig_counts(ig_context* ctx, uint64_t* n_instr, uint64_t* n_bind, uint64_t* n_edge, uint64_t* n_tasks);
+
+/* Copy records into host arrays, continuing from the previous fetch. */
+ig_status ig_fetch_instructions(ig_context* ctx, ig_instruction* dst, size_t cap, size_t* n_out);
+ig_status ig_fetch_bindings(ig_context* ctx, ig_binding* dst, size_t cap, size_t* n_out);
+ig_status ig_fetch_edges(ig_context* ctx, ig_edge* dst, size_t cap, size_t* n_out);
+ig_status ig_fetch_task_status(ig_context* ctx, int32_t* dst, size_t cap, size_t* n_out);
+
+/* Per-kind counts, resizes, warnings and the three record digests, all
+ * computed on the device. */
+ig_status ig_stats_get(ig_context* ctx, ig_stats* out);
+
+const char* ig_status_str(ig_status st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

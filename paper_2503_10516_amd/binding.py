@@ -1,0 +1,343 @@
+"""ctypes binding of libig (include/ig.h): argument marshalling only.
+
+Every step of instruction-graph generation runs in the HIP kernels of
+libig.so; this module builds descriptors, hands over device memory and the
+stream (from PyTorch, when a GPU is present) and copies records out.  If the
+library is missing the import of `lib()` fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG_DIR, "libig.so")
+
+INSTR_DTYPE = np.dtype([
+    ("id", "<u8"), ("kind", "u1"), ("flags", "u1"), ("mem", "<u2"), ("src_mem", "<u2"),
+    ("pad0", "<u2"), ("task", "<u4"), ("chunk", "<u4"), ("buffer", "<u4"), ("pad1", "<u4"),
+    ("alloc", "<u8"), ("src_alloc", "<u8"), ("min", "<i8", (3,)), ("max", "<i8", (3,)),
+])
+BIND_DTYPE = np.dtype([("instr", "<u8"), ("access", "<u4"), ("pad", "<u4"), ("alloc", "<u8")])
+EDGE_DTYPE = np.dtype([("from", "<u8"), ("to", "<u8"), ("kinds", "<u4"), ("pad", "<u4")])
+
+IG_OK, IG_W_UNINIT_READ, IG_E_INVALID, IG_E_OVERLAPPING_WRITE, IG_E_CAPACITY, IG_E_DEVICE, IG_E_BUSY = \
+    0, 1, -1, -2, -3, -4, -5
+
+
+class IgError(RuntimeError):
+    def __init__(self, where: str, status: int):
+        super().__init__(f"{where} failed: {status}")
+        self.status = status
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("min", ctypes.c_int64 * 3), ("max", ctypes.c_int64 * 3)]
+
+
+class Access(ctypes.Structure):
+    _fields_ = [("buffer", ctypes.c_uint32), ("mode", ctypes.c_uint8), ("mapper", ctypes.c_uint8),
+                ("slice_dim", ctypes.c_uint8), ("pad", ctypes.c_uint8),
+                ("radius", ctypes.c_int64 * 3), ("fixed", Box)]
+
+
+class TaskDesc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_uint32), ("n_access", ctypes.c_uint32), ("box", Box),
+                ("access", Access * 8)]
+
+
+class ContextDesc(ctypes.Structure):
+    _fields_ = [("nodes", ctypes.c_uint32), ("devices_per_node", ctypes.c_uint32),
+                ("chunks", ctypes.c_uint32), ("horizon_step", ctypes.c_uint32),
+                ("lookahead", ctypes.c_uint32), ("flush_horizons", ctypes.c_uint32),
+                ("queue_cap", ctypes.c_uint32), ("threads", ctypes.c_uint32),
+                ("cap_commands", ctypes.c_uint64), ("cap_instructions", ctypes.c_uint64),
+                ("cap_edges", ctypes.c_uint64), ("cap_state_words", ctypes.c_uint64),
+                ("cap_unit", ctypes.c_uint64),
+                ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_uint64),
+                ("stream", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_instructions", ctypes.c_uint64), ("n_bindings", ctypes.c_uint64),
+                ("n_edges", ctypes.c_uint64), ("per_kind", ctypes.c_uint64 * 8),
+                ("per_dep", ctypes.c_uint64 * 5), ("resizes", ctypes.c_uint64),
+                ("warnings", ctypes.c_uint64), ("tasks_submitted", ctypes.c_uint64),
+                ("tasks_rejected", ctypes.c_uint64), ("digest_instructions", ctypes.c_uint64),
+                ("digest_bindings", ctypes.c_uint64), ("digest_edges", ctypes.c_uint64),
+                ("commands_analysed", ctypes.c_uint64), ("launches", ctypes.c_uint64)]
+
+
+EXPORTS = [
+    "ig_arena_bytes", "ig_context_create", "ig_context_destroy", "ig_buffer_create",
+    "ig_buffer_destroy", "ig_submit_task", "ig_submit_tasks", "ig_epoch", "ig_shutdown",
+    "ig_flush_window", "ig_batch_flush", "ig_sync", "ig_rewind", "ig_counts",
+    "ig_fetch_instructions", "ig_fetch_bindings", "ig_fetch_edges", "ig_fetch_task_status",
+    "ig_stats_get", "ig_status_str",
+]
+
+_libs: Dict[str, ctypes.CDLL] = {}
+
+
+def lib(path: Optional[str] = None) -> ctypes.CDLL:
+    """Load libig (the HIP build) -- or, for CPU tests only, another build of
+    the same ABI named explicitly by `path`."""
+    path = path or LIB_PATH
+    if path in _libs:
+        return _libs[path]
+    if not os.path.exists(path):
+        raise ImportError(f"libig not built: {path} is missing (run __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    L.ig_arena_bytes.argtypes = [P(ContextDesc), P(ctypes.c_uint64)]
+    L.ig_context_create.argtypes = [P(ContextDesc), P(vp)]
+    L.ig_context_destroy.argtypes = [vp]
+    L.ig_buffer_create.argtypes = [vp, ctypes.c_uint32, P(ctypes.c_int64), ctypes.c_uint32, ctypes.c_uint32,
+                                   P(ctypes.c_uint32)]
+    L.ig_buffer_destroy.argtypes = [vp, ctypes.c_uint32]
+    L.ig_submit_task.argtypes = [vp, P(TaskDesc), P(ctypes.c_uint64)]
+    L.ig_submit_tasks.argtypes = [vp, P(TaskDesc), ctypes.c_size_t, P(ctypes.c_uint64)]
+    for n in ("ig_epoch", "ig_shutdown", "ig_flush_window", "ig_sync", "ig_rewind"):
+        getattr(L, n).argtypes = [vp]
+    L.ig_batch_flush.argtypes = [P(vp), ctypes.c_size_t, vp]
+    L.ig_counts.argtypes = [vp] + [P(ctypes.c_uint64)] * 4
+    for n in ("ig_fetch_instructions", "ig_fetch_bindings", "ig_fetch_edges", "ig_fetch_task_status"):
+        getattr(L, n).argtypes = [vp, vp, ctypes.c_size_t, P(ctypes.c_size_t)]
+    L.ig_stats_get.argtypes = [vp, P(Stats)]
+    L.ig_status_str.argtypes = [ctypes.c_int32]
+    L.ig_status_str.restype = ctypes.c_char_p
+    for n in EXPORTS:
+        if n != "ig_status_str":
+            getattr(L, n).restype = ctypes.c_int32
+    _libs[path] = L
+    return L
+
+
+def _box(lo, hi) -> Box:
+    b = Box()
+    for d in range(3):
+        b.min[d] = int(lo[d])
+        b.max[d] = int(hi[d])
+    return b
+
+
+def task_desc(task) -> TaskDesc:
+    td = TaskDesc()
+    td.dims = task.dims
+    td.n_access = len(task.accesses)
+    td.box = _box(task.lo, task.hi)
+    for j, a in enumerate(task.accesses):
+        ad = td.access[j]
+        ad.buffer = a.buffer
+        ad.mode = a.mode
+        ad.mapper = a.mapper
+        ad.slice_dim = a.slice_dim
+        for d in range(3):
+            ad.radius[d] = a.radius[d]
+        ad.fixed = _box(a.fixed_lo, a.fixed_hi)
+    return td
+
+
+def estimate_caps(stream) -> Dict[str, int]:
+    """Generous output capacities for a stream, from its shape only: a task
+    emits at most one kernel per chunk; a read whose region is independent of
+    the chunk (all, slice, fixed) can need a copy from every chunk's producer
+    into every device, other reads a few boundary copies per chunk."""
+    C = stream.chunks
+    n_dev = stream.nodes * stream.devices
+    instr = 64 + n_dev * 64 * 4
+    for c in stream.cmds:
+        if c[0] != "task":
+            continue
+        instr += C
+        for a in c[1].accesses:
+            if a.mode & 1:
+                instr += C * min(C, n_dev + 1) if a.mapper in (2, 3, 4) else 6 * C
+            instr += 2
+    instr = min(instr, 0xFFFF0000)
+    return dict(cap_commands=len(stream.cmds) + 8, cap_instructions=instr, cap_edges=6 * instr)
+
+
+class Context:
+    """One stream analysed by libig.
+
+    device: "cuda" (default when torch sees a GPU) allocates the arena as a
+    torch tensor and uses torch's current stream; "host" lets the library
+    allocate (only meaningful for the CPU test build)."""
+
+    def __init__(self, nodes, devices, chunks=0, horizon_step=0, lookahead=1, flush_horizons=0,
+                 queue_cap=0, threads=0, lib_path=None, device=None, cap_commands=0,
+                 cap_instructions=0, cap_edges=0, cap_state_words=0, cap_unit=0, stream=None):
+        self.L = lib(lib_path)
+        d = ContextDesc()
+        d.nodes, d.devices_per_node, d.chunks = nodes, devices, chunks
+        d.horizon_step, d.lookahead, d.flush_horizons, d.queue_cap = horizon_step, lookahead, flush_horizons, queue_cap
+        d.threads = threads
+        d.cap_commands, d.cap_instructions, d.cap_edges = cap_commands, cap_instructions, cap_edges
+        d.cap_state_words, d.cap_unit = cap_state_words, cap_unit
+        self.arena = None
+        if device is None:
+            device = "cuda" if lib_path is None else "host"
+        self.device = device
+        if device == "cuda":
+            import torch
+            nbytes = ctypes.c_uint64()
+            st = self.L.ig_arena_bytes(ctypes.byref(d), ctypes.byref(nbytes))
+            if st != 0:
+                raise IgError("ig_arena_bytes", st)
+            self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+            d.arena = self.arena.data_ptr()
+            d.arena_bytes = nbytes.value
+            s = stream if stream is not None else torch.cuda.current_stream()
+            d.stream = s.cuda_stream
+            self.torch_stream = s
+        self.desc = d
+        self.h = ctypes.c_void_p()
+        st = self.L.ig_context_create(ctypes.byref(d), ctypes.byref(self.h))
+        if st != 0:
+            raise IgError("ig_context_create", st)
+
+    # --- recording ---------------------------------------------------------
+    def buffer_create(self, dims, extent, elem_size, init) -> int:
+        ext = (ctypes.c_int64 * 3)(*extent)
+        out = ctypes.c_uint32()
+        st = self.L.ig_buffer_create(self.h, dims, ext, elem_size, init, ctypes.byref(out))
+        if st != 0:
+            raise IgError("ig_buffer_create", st)
+        return out.value
+
+    def submit(self, task) -> int:
+        td = task_desc(task)
+        out = ctypes.c_uint64()
+        st = self.L.ig_submit_task(self.h, ctypes.byref(td), ctypes.byref(out))
+        if st != 0:
+            raise IgError("ig_submit_task", st)
+        return out.value
+
+    def buffer_destroy(self, b):
+        st = self.L.ig_buffer_destroy(self.h, b)
+        if st != 0:
+            raise IgError("ig_buffer_destroy", st)
+
+    def epoch(self):
+        st = self.L.ig_epoch(self.h)
+        if st != 0:
+            raise IgError("ig_epoch", st)
+
+    def shutdown(self):
+        st = self.L.ig_shutdown(self.h)
+        if st != 0:
+            raise IgError("ig_shutdown", st)
+
+    def record(self, stream) -> None:
+        for c in stream.cmds:
+            if c[0] == "buffer":
+                self.buffer_create(c[1], c[2], c[3], c[4])
+            elif c[0] == "task":
+                self.submit(c[1])
+            elif c[0] == "epoch":
+                self.epoch()
+            elif c[0] == "destroy":
+                self.buffer_destroy(c[1])
+            elif c[0] == "shutdown":
+                self.shutdown()
+            else:
+                raise ValueError(c[0])
+
+    # --- analysis ----------------------------------------------------------
+    def flush(self):
+        st = self.L.ig_flush_window(self.h)
+        if st != 0:
+            raise IgError("ig_flush_window", st)
+
+    def sync(self) -> int:
+        return int(self.L.ig_sync(self.h))
+
+    def rewind(self):
+        st = self.L.ig_rewind(self.h)
+        if st != 0:
+            raise IgError("ig_rewind", st)
+
+    def counts(self):
+        v = [ctypes.c_uint64() for _ in range(4)]
+        st = self.L.ig_counts(self.h, *[ctypes.byref(x) for x in v])
+        if st != 0:
+            raise IgError("ig_counts", st)
+        return tuple(x.value for x in v)
+
+    def _fetch(self, fn, dtype, n):
+        arr = np.zeros(n, dtype=dtype)
+        got = ctypes.c_size_t()
+        st = fn(self.h, arr.ctypes.data_as(ctypes.c_void_p), n, ctypes.byref(got))
+        if st != 0:
+            raise IgError("fetch", st)
+        return arr[: got.value]
+
+    def fetch_all(self) -> Dict[str, np.ndarray]:
+        ni, nb, ne, nt = self.counts()
+        return dict(
+            instructions=self._fetch(self.L.ig_fetch_instructions, INSTR_DTYPE, ni),
+            bindings=self._fetch(self.L.ig_fetch_bindings, BIND_DTYPE, nb),
+            edges=self._fetch(self.L.ig_fetch_edges, EDGE_DTYPE, ne),
+            status=self._fetch(self.L.ig_fetch_task_status, np.dtype("<i4"), nt),
+        )
+
+    def stats(self) -> Dict[str, object]:
+        s = Stats()
+        st = self.L.ig_stats_get(self.h, ctypes.byref(s))
+        if st != 0:
+            raise IgError("ig_stats_get", st)
+        out = {k: getattr(s, k) for k, _ in Stats._fields_}
+        out["per_kind"] = list(s.per_kind)
+        out["per_dep"] = list(s.per_dep)
+        return out
+
+    def close(self):
+        if self.h:
+            self.L.ig_context_destroy(self.h)
+            self.h = ctypes.c_void_p()
+        self.arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_context(stream, lib_path=None, device=None, threads=0, **caps) -> Context:
+    kw = stream.desc()
+    est = estimate_caps(stream)
+    est.update(caps)
+    return Context(lib_path=lib_path, device=device, threads=threads, **kw, **est)
+
+
+def run_stream(stream, lib_path=None, device=None, threads=0, fetch=True, **caps) -> Dict[str, object]:
+    """Record, analyse and (optionally) fetch one stream."""
+    ctx = make_context(stream, lib_path=lib_path, device=device, threads=threads, **caps)
+    ctx.record(stream)
+    t0 = time.perf_counter()
+    ctx.flush()
+    st = ctx.sync()
+    elapsed = time.perf_counter() - t0
+    if st != 0:
+        ctx.close()
+        raise IgError("analysis", st)
+    out: Dict[str, object] = {"seconds": elapsed, "stats": ctx.stats()}
+    if fetch:
+        out.update(ctx.fetch_all())
+    ctx.close()
+    return out
+
+
+def batch_flush(contexts: Sequence[Context], stream=None) -> None:
+    L = contexts[0].L
+    arr = (ctypes.c_void_p * len(contexts))(*[c.h for c in contexts])
+    st = L.ig_batch_flush(arr, len(contexts), None if stream is None else stream.cuda_stream)
+    if st != 0:
+        raise IgError("ig_batch_flush", st)

@@ -1,0 +1,586 @@
+// ig_api.cpp -- host side of libig: argument validation, command recording,
+// device-memory layout, launches and record fetch.  No analysis happens
+// here; every step of instruction-graph generation runs in ig_kernels.hip.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ig_dev.h"
+
+using namespace igd;
+
+struct Caps {
+    u32 nodes, devices, chunks, per_dev, n_dev, n_mem, mw;
+    u32 horizon_step, lookahead, flush_horizons, queue_cap, threads, n_workers;
+    u32 cap_cmds, cap_allocs, cap_queue, cap_heap, cap_rb, cap_unit, cap_scr, cap_src, cap_box;
+    u64 cap_instr, cap_edges, cap_binds;
+    u64 pack_bytes;
+};
+
+struct ig_context {
+    ig_context_desc d;
+    Caps k;
+    DevCtx h;          // host view of the device context (device pointers)
+    DevCtx* dctx;      // device copy
+    DevCtx** dptrs;    // device array {dctx}
+    DevStats* dstats;  // device
+    void* pack;        // device staging for fetch
+    char* arena;
+    bool own_arena;
+    u64 arena_bytes;
+    void* stream;
+    std::vector<DevCmd> cmds;
+    size_t uploaded;
+    struct HBuf {
+        u32 dims;
+        i64 ext[3];
+        bool alive;
+    };
+    std::vector<HBuf> bufs;
+    u64 n_tasks;
+    bool shut;
+    u64 cur_i, cur_b, cur_e, cur_t;
+    Scalars s;
+    bool s_valid;
+    u64 launches;
+};
+
+static bool make_caps(const ig_context_desc* d, Caps& k) {
+    if (!d || d->nodes == 0 || d->devices_per_node == 0) return false;
+    if ((u64)d->nodes * d->devices_per_node > IG_MAX_DEVICES) return false;
+    k.nodes = d->nodes;
+    k.devices = d->devices_per_node;
+    k.n_dev = k.nodes * k.devices;
+    k.chunks = d->chunks ? d->chunks : k.n_dev;
+    if (k.chunks % k.n_dev != 0 || k.chunks > MAX_CHUNKS) return false;
+    k.per_dev = k.chunks / k.n_dev;
+    k.n_mem = k.n_dev + 2;
+    k.mw = (k.n_mem + 63) / 64;
+    k.horizon_step = d->horizon_step ? d->horizon_step : 4;
+    if (d->lookahead > 1) return false;
+    k.lookahead = d->lookahead;
+    k.flush_horizons = d->flush_horizons ? d->flush_horizons : 2;
+    k.queue_cap = d->queue_cap;
+    k.threads = d->threads ? d->threads : 256;
+    if (k.threads < 32 || k.threads > MAX_THREADS || (k.threads & 31)) return false;
+    k.n_workers = std::min(k.threads, k.n_mem);
+    k.cap_cmds = (u32)(d->cap_commands ? d->cap_commands : 65536);
+    k.cap_instr = d->cap_instructions ? d->cap_instructions : (1ull << 20);
+    k.cap_edges = d->cap_edges ? d->cap_edges : 4 * k.cap_instr;
+    k.cap_binds = 2 * k.cap_instr + 64;
+    if (k.cap_instr >= 0xFFFFFFF0ull || k.cap_edges >= (1ull << 40)) return false;
+    k.cap_heap = (u32)(d->cap_state_words ? d->cap_state_words : (1u << 24));
+    k.cap_rb = std::max<u32>(1024, k.cap_heap / 8);
+    k.cap_unit = (u32)(d->cap_unit ? d->cap_unit : (1u << 18));
+    k.cap_queue = 2 * k.cap_cmds + 2;
+    k.cap_allocs = 1u << 16;
+    k.cap_scr = 8192;
+    k.cap_src = 4096;
+    k.cap_box = 2048;
+    k.pack_bytes = 1ull << 24;
+    return true;
+}
+
+struct Tail {
+    DevCtx* dctx;
+    DevCtx** dptrs;
+    DevStats* dstats;
+    void* pack;
+};
+
+// Lay out every device array of one context; with base == nullptr only the
+// size is computed.
+static u64 carve(const Caps& k, char* base, DevCtx* h, Tail* tail = nullptr) {
+    u64 off = 0;
+    auto take = [&](u64 bytes) -> char* {
+        off = (off + 255) & ~255ull;
+        char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+#define TAKE(field, type, count) h->field = (type*)take(sizeof(type) * (u64)(count))
+    const u64 bm = (u64)MAX_BUF * k.n_mem;
+    TAKE(cmds, DevCmd, k.cap_cmds);
+    TAKE(i_kind, u8, k.cap_instr);
+    TAKE(i_flags, u8, k.cap_instr);
+    TAKE(i_mem, u16, k.cap_instr);
+    TAKE(i_src_mem, u16, k.cap_instr);
+    TAKE(i_task, u32, k.cap_instr);
+    TAKE(i_chunk, u32, k.cap_instr);
+    TAKE(i_buffer, u32, k.cap_instr);
+    TAKE(i_alloc, u32, k.cap_instr);
+    TAKE(i_src_alloc, u32, k.cap_instr);
+    TAKE(i_box, i64, 6 * k.cap_instr);
+    TAKE(e_from, u32, k.cap_edges);
+    TAKE(e_to, u32, k.cap_edges);
+    TAKE(e_kinds, u8, k.cap_edges);
+    TAKE(b_instr, u32, k.cap_binds);
+    TAKE(b_access, u32, k.cap_binds);
+    TAKE(b_alloc, u32, k.cap_binds);
+    TAKE(has_succ, u8, k.cap_instr);
+    TAKE(task_status, i32, k.cap_cmds);
+    TAKE(bufs, DBuf, MAX_BUF);
+    TAKE(allocs, DAlloc, k.cap_allocs);
+    TAKE(live_n, u32, bm);
+    TAKE(live, u32, bm * MAX_LIVE);
+    TAKE(plan_n, u32, bm);
+    TAKE(plan, i64, bm * MAX_PLAN * 6);
+    TAKE(queue, u32, k.cap_queue);
+    TAKE(heap, u32, k.cap_heap);
+    TAKE(heap_free, u32, 32);
+    TAKE(rb, u32, (u64)k.cap_rb * 8);
+    TAKE(rb_free, u32, k.n_mem);
+    TAKE(reg, Region, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
+    TAKE(chunk_lo, i64, MAX_CHUNKS);
+    TAKE(chunk_hi, i64, MAX_CHUNKS);
+    TAKE(cons_off, u32, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
+    TAKE(cons_cnt, u32, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
+    TAKE(copies, CopyRec, k.cap_unit);
+    TAKE(dev_cnt, u32, k.n_dev);
+    TAKE(dev_base, u32, k.n_dev);
+    TAKE(kdev_cnt, u32, k.n_dev);
+    TAKE(kdev_base, u32, k.n_dev);
+    TAKE(inbox_cnt, u32, k.n_mem);
+    TAKE(inbox_off, u32, k.n_mem);
+    TAKE(inbox_cur, u32, k.n_mem);
+    TAKE(inbox, InboxRec, k.cap_unit);
+    TAKE(tab_off, u32, k.cap_unit + 1);
+    TAKE(tab_cnt, u32, k.cap_unit + 1);
+    TAKE(stage_from, u32, (u64)k.cap_unit * 8);
+    TAKE(stage_kind, u8, (u64)k.cap_unit * 8);
+    TAKE(pair_flag, u32, bm);
+    TAKE(pair_cnt, u32, bm);
+    TAKE(pair_acnt, u32, bm);
+    TAKE(miss_n, u32, 4);
+    TAKE(miss_val, i64, k.cap_scr);
+    TAKE(miss_bd, u32, k.cap_scr);
+    TAKE(remap, u32, 3ull * k.cap_scr);
+    TAKE(wk_key, u64, (u64)k.n_workers * k.cap_scr);
+    TAKE(wk_val, u32, (u64)k.n_workers * k.cap_scr);
+    TAKE(wk_key2, u64, (u64)k.n_workers * k.cap_scr);
+    TAKE(wk_val2, u32, (u64)k.n_workers * k.cap_scr);
+    TAKE(wk_src, u64, (u64)k.n_workers * k.cap_src);
+    TAKE(wk_src2, u64, (u64)k.n_workers * k.cap_src);
+    TAKE(wk_box, i64, (u64)k.n_workers * k.cap_box * 6);
+#undef TAKE
+    Tail t;
+    t.dctx = (DevCtx*)take(sizeof(DevCtx));         // the device copy of the context
+    t.dptrs = (DevCtx**)take(sizeof(DevCtx*) * 2);  // pointer array for a single-context launch
+    t.dstats = (DevStats*)take(sizeof(DevStats));
+    t.pack = take(k.pack_bytes);                    // fetch staging
+    if (tail) *tail = t;
+    return (off + 255) & ~255ull;
+}
+
+static void fill_config(const Caps& k, DevCtx& h) {
+    h.nodes = k.nodes;
+    h.devices = k.devices;
+    h.chunks = k.chunks;
+    h.per_dev = k.per_dev;
+    h.n_dev = k.n_dev;
+    h.n_mem = k.n_mem;
+    h.mw = k.mw;
+    h.horizon_step = k.horizon_step;
+    h.lookahead = k.lookahead;
+    h.flush_horizons = k.flush_horizons;
+    h.queue_cap = k.queue_cap;
+    h.threads = k.threads;
+    h.n_workers = k.n_workers;
+    h.cap_cmds = k.cap_cmds;
+    h.cap_allocs = k.cap_allocs;
+    h.cap_queue = k.cap_queue;
+    h.cap_heap = k.cap_heap;
+    h.cap_rb = k.cap_rb;
+    h.cap_unit = k.cap_unit;
+    h.cap_scr = k.cap_scr;
+    h.cap_src = k.cap_src;
+    h.cap_box = k.cap_box;
+    h.cap_instr = k.cap_instr;
+    h.cap_edges = k.cap_edges;
+    h.cap_binds = k.cap_binds;
+    h.cmd_end = 0;
+    std::memset(&h.s, 0, sizeof h.s);
+}
+
+template <class Rec, class Launch>
+static ig_status fetch_records(ig_context* c, u64 total, u64& cursor, Rec* dst, size_t cap, size_t* n_out, Launch launch) {
+    const u64 n = std::min<u64>(cap, total - cursor);
+    const u64 per = c->k.pack_bytes / sizeof(Rec);
+    u64 done = 0;
+    while (done < n) {
+        const u64 m = std::min(per, n - done);
+        if (launch(cursor + done, m, (Rec*)c->pack) != 0) return IG_E_DEVICE;
+        if (igrt::copy_d2h(dst + done, c->pack, m * sizeof(Rec), c->stream) != 0) return IG_E_DEVICE;
+        if (igrt::stream_sync(c->stream) != 0) return IG_E_DEVICE;
+        done += m;
+    }
+    cursor += n;
+    if (n_out) *n_out = (size_t)n;
+    return IG_OK;
+}
+
+extern "C" {
+
+const char* ig_status_str(ig_status st) {
+    switch (st) {
+        case IG_OK: return "ok";
+        case IG_W_UNINIT_READ: return "warning: read of uninitialised data";
+        case IG_E_INVALID: return "invalid argument";
+        case IG_E_OVERLAPPING_WRITE: return "overlapping writes";
+        case IG_E_CAPACITY: return "capacity exceeded";
+        case IG_E_DEVICE: return "device error";
+        case IG_E_BUSY: return "busy";
+        default: return "unknown status";
+    }
+}
+
+ig_status ig_arena_bytes(const ig_context_desc* desc, uint64_t* bytes) {
+    Caps k;
+    if (!make_caps(desc, k) || !bytes) return IG_E_INVALID;
+    DevCtx h;
+    *bytes = carve(k, nullptr, &h);
+    return IG_OK;
+}
+
+ig_status ig_context_create(const ig_context_desc* desc, ig_context** out) {
+    Caps k;
+    if (!out || !make_caps(desc, k)) return IG_E_INVALID;
+    ig_context* c = new (std::nothrow) ig_context();
+    if (!c) return IG_E_CAPACITY;
+    c->d = *desc;
+    c->k = k;
+    c->stream = desc->stream;
+    DevCtx probe;
+    const u64 need = carve(k, nullptr, &probe);
+    if (desc->arena) {
+        if (desc->arena_bytes < need) {
+            delete c;
+            return IG_E_CAPACITY;
+        }
+        c->arena = (char*)desc->arena;
+        c->own_arena = false;
+    } else {
+        void* p = nullptr;
+        if (igrt::dev_malloc(&p, need) != 0) {
+            delete c;
+            return IG_E_DEVICE;
+        }
+        c->arena = (char*)p;
+        c->own_arena = true;
+    }
+    c->arena_bytes = need;
+    std::memset(&c->h, 0, sizeof c->h);
+    Tail tail;
+    carve(k, c->arena, &c->h, &tail);
+    c->dctx = tail.dctx;
+    c->dptrs = tail.dptrs;
+    c->dstats = tail.dstats;
+    c->pack = tail.pack;
+    fill_config(k, c->h);
+    if (igrt::copy_h2d(c->dctx, &c->h, sizeof(DevCtx), c->stream) != 0 ||
+        igrt::copy_h2d(c->dptrs, &c->dctx, sizeof(DevCtx*), c->stream) != 0 ||
+        igrt::stream_sync(c->stream) != 0) {
+        if (c->own_arena) igrt::dev_free(c->arena);
+        delete c;
+        return IG_E_DEVICE;
+    }
+    c->uploaded = 0;
+    c->n_tasks = 0;
+    c->shut = false;
+    c->cur_i = c->cur_b = c->cur_e = c->cur_t = 0;
+    std::memset(&c->s, 0, sizeof c->s);
+    c->s_valid = false;
+    c->launches = 0;
+    *out = c;
+    return IG_OK;
+}
+
+ig_status ig_context_destroy(ig_context* c) {
+    if (!c) return IG_E_INVALID;
+    igrt::stream_sync(c->stream);
+    if (c->own_arena) igrt::dev_free(c->arena);
+    delete c;
+    return IG_OK;
+}
+
+static bool can_record(ig_context* c) { return c && !c->shut && c->cmds.size() < c->k.cap_cmds; }
+
+ig_status ig_buffer_create(ig_context* c, uint32_t dims, const int64_t extent[3], uint32_t elem_size, uint32_t init,
+                           uint32_t* out_buffer) {
+    if (!c || c->shut || !extent || dims < 1 || dims > 3 || elem_size == 0 || init > 1) return IG_E_INVALID;
+    if (c->bufs.size() >= MAX_BUF || !can_record(c)) return IG_E_CAPACITY;
+    DevCmd cmd;
+    std::memset(&cmd, 0, sizeof cmd);
+    cmd.kind = CMD_BUFFER;
+    cmd.arg = (u32)c->bufs.size();
+    cmd.dims = dims;
+    cmd.elem_size = elem_size;
+    cmd.init = init;
+    ig_context::HBuf hb;
+    hb.dims = dims;
+    hb.alive = true;
+    for (u32 d = 0; d < 3; ++d) {
+        if (d < dims) {
+            if (extent[d] < 1 || extent[d] > ((int64_t)1 << 40)) return IG_E_INVALID;
+            cmd.ext[d] = extent[d];
+        } else {
+            cmd.ext[d] = 1;
+        }
+        hb.ext[d] = cmd.ext[d];
+    }
+    c->cmds.push_back(cmd);
+    c->bufs.push_back(hb);
+    if (out_buffer) *out_buffer = cmd.arg;
+    return IG_OK;
+}
+
+ig_status ig_buffer_destroy(ig_context* c, uint32_t b) {
+    if (!c || c->shut || b >= c->bufs.size() || !c->bufs[b].alive) return IG_E_INVALID;
+    if (!can_record(c)) return IG_E_CAPACITY;
+    DevCmd cmd;
+    std::memset(&cmd, 0, sizeof cmd);
+    cmd.kind = CMD_DESTROY;
+    cmd.arg = b;
+    c->cmds.push_back(cmd);
+    c->bufs[b].alive = false;
+    return IG_OK;
+}
+
+static ig_status validate_task(const ig_context* c, const ig_task_desc* t) {
+    if (!t || t->dims < 1 || t->dims > 3 || t->n_access > IG_MAX_ACCESS) return IG_E_INVALID;
+    const int64_t lim = (int64_t)1 << 40;
+    for (u32 d = 0; d < 3; ++d) {
+        if (d < t->dims) {
+            if (t->box.min[d] > t->box.max[d] || t->box.min[d] < -lim || t->box.max[d] > lim) return IG_E_INVALID;
+        } else if (t->box.min[d] != 0 || t->box.max[d] != 1) {
+            return IG_E_INVALID;
+        }
+    }
+    for (u32 j = 0; j < t->n_access; ++j) {
+        const ig_access& a = t->access[j];
+        if (a.buffer >= c->bufs.size() || !c->bufs[a.buffer].alive) return IG_E_INVALID;
+        if (a.mode < 1 || a.mode > 3 || a.mapper > IG_MAP_FIXED) return IG_E_INVALID;
+        const u32 bd = c->bufs[a.buffer].dims;
+        const bool needs = a.mapper == IG_MAP_ONE_TO_ONE || a.mapper == IG_MAP_NEIGHBORHOOD || a.mapper == IG_MAP_SLICE;
+        if (needs && bd != t->dims) return IG_E_INVALID;
+        if (a.mapper == IG_MAP_SLICE && a.slice_dim >= bd) return IG_E_INVALID;
+        if (a.mapper == IG_MAP_NEIGHBORHOOD)
+            for (u32 d = 0; d < bd; ++d)
+                if (a.radius[d] < 0 || a.radius[d] > lim) return IG_E_INVALID;
+        if (a.mapper == IG_MAP_FIXED)
+            for (u32 d = 0; d < bd; ++d)
+                if (a.fixed.min[d] > a.fixed.max[d] || a.fixed.min[d] < -lim || a.fixed.max[d] > lim)
+                    return IG_E_INVALID;
+    }
+    return IG_OK;
+}
+
+ig_status ig_submit_task(ig_context* c, const ig_task_desc* t, uint64_t* out_task) {
+    if (!c || c->shut) return IG_E_INVALID;
+    const ig_status v = validate_task(c, t);
+    if (v != IG_OK) return v;
+    if (!can_record(c)) return IG_E_CAPACITY;
+    DevCmd cmd;
+    std::memset(&cmd, 0, sizeof cmd);
+    cmd.kind = CMD_TASK;
+    cmd.arg = (u32)c->n_tasks;
+    cmd.task = *t;
+    // normalise the unused parts of the descriptor
+    for (u32 j = t->n_access; j < IG_MAX_ACCESS; ++j) std::memset(&cmd.task.access[j], 0, sizeof(ig_access));
+    c->cmds.push_back(cmd);
+    if (out_task) *out_task = c->n_tasks;
+    ++c->n_tasks;
+    return IG_OK;
+}
+
+ig_status ig_submit_tasks(ig_context* c, const ig_task_desc* t, size_t n, uint64_t* out_first) {
+    if (!c || (!t && n)) return IG_E_INVALID;
+    if (out_first) *out_first = c->n_tasks;
+    for (size_t i = 0; i < n; ++i) {
+        const ig_status st = ig_submit_task(c, t + i, nullptr);
+        if (st != IG_OK) return st;
+    }
+    return IG_OK;
+}
+
+static ig_status record_simple(ig_context* c, u32 kind) {
+    if (!c || c->shut) return IG_E_INVALID;
+    if (!can_record(c)) return IG_E_CAPACITY;
+    DevCmd cmd;
+    std::memset(&cmd, 0, sizeof cmd);
+    cmd.kind = kind;
+    c->cmds.push_back(cmd);
+    return IG_OK;
+}
+
+ig_status ig_epoch(ig_context* c) { return record_simple(c, CMD_EPOCH); }
+
+ig_status ig_shutdown(ig_context* c) {
+    const ig_status st = record_simple(c, CMD_SHUTDOWN);
+    if (st == IG_OK) {
+        c->shut = true;
+        for (auto& b : c->bufs) b.alive = false;
+    }
+    return st;
+}
+
+static ig_status upload(ig_context* c) {
+    if (c->uploaded == c->cmds.size()) return IG_OK;
+    // commands are appended only; a running analysis reads below cmd_end
+    if (igrt::stream_sync(c->stream) != 0) return IG_E_DEVICE;
+    const size_t n = c->cmds.size() - c->uploaded;
+    if (igrt::copy_h2d(c->h.cmds + c->uploaded, c->cmds.data() + c->uploaded, n * sizeof(DevCmd), c->stream) != 0)
+        return IG_E_DEVICE;
+    const u32 end = (u32)c->cmds.size();
+    if (igrt::copy_h2d(&c->dctx->cmd_end, &end, sizeof(u32), c->stream) != 0) return IG_E_DEVICE;
+    if (igrt::stream_sync(c->stream) != 0) return IG_E_DEVICE;
+    c->uploaded = c->cmds.size();
+    c->h.cmd_end = end;
+    return IG_OK;
+}
+
+ig_status ig_flush_window(ig_context* c) {
+    if (!c) return IG_E_INVALID;
+    const ig_status st = upload(c);
+    if (st != IG_OK) return st;
+    if (igrt::launch_analyse(c->dptrs, 1, c->k.threads, c->stream) != 0) return IG_E_DEVICE;
+    c->s_valid = false;
+    ++c->launches;
+    return IG_OK;
+}
+
+ig_status ig_batch_flush(ig_context* const* ctxs, size_t n, void* stream) {
+    if (!ctxs || n == 0) return IG_E_INVALID;
+    const u32 threads = ctxs[0]->k.threads;
+    for (size_t i = 0; i < n; ++i) {
+        if (!ctxs[i] || ctxs[i]->k.threads != threads) return IG_E_INVALID;
+        const ig_status st = upload(ctxs[i]);
+        if (st != IG_OK) return st;
+    }
+    void* s = stream ? stream : ctxs[0]->stream;
+    // the pointer table lives in the first context's staging area
+    std::vector<DevCtx*> ptrs(n);
+    for (size_t i = 0; i < n; ++i) ptrs[i] = ctxs[i]->dctx;
+    if (n * sizeof(DevCtx*) > ctxs[0]->k.pack_bytes) return IG_E_CAPACITY;
+    DevCtx** table = (DevCtx**)ctxs[0]->pack;
+    if (igrt::copy_h2d(table, ptrs.data(), n * sizeof(DevCtx*), s) != 0) return IG_E_DEVICE;
+    if (igrt::stream_sync(s) != 0) return IG_E_DEVICE;
+    if (igrt::launch_analyse(table, (unsigned)n, threads, s) != 0) return IG_E_DEVICE;
+    for (size_t i = 0; i < n; ++i) {
+        ctxs[i]->s_valid = false;
+        ++ctxs[i]->launches;
+    }
+    return IG_OK;
+}
+
+static ig_status refresh(ig_context* c) {
+    if (c->s_valid) return IG_OK;
+    if (igrt::stream_sync(c->stream) != 0) return IG_E_DEVICE;
+    if (igrt::copy_d2h(&c->s, &c->dctx->s, sizeof(Scalars), c->stream) != 0) return IG_E_DEVICE;
+    if (igrt::stream_sync(c->stream) != 0) return IG_E_DEVICE;
+    c->s_valid = true;
+    return IG_OK;
+}
+
+ig_status ig_sync(ig_context* c) {
+    if (!c) return IG_E_INVALID;
+    const ig_status st = refresh(c);
+    if (st != IG_OK) return st;
+    if (c->s.error) return c->s.error;
+    return IG_OK;
+}
+
+ig_status ig_rewind(ig_context* c) {
+    if (!c) return IG_E_INVALID;
+    Scalars z;
+    std::memset(&z, 0, sizeof z);
+    if (igrt::memset_d(&c->dctx->s, 0, sizeof(Scalars), c->stream) != 0) return IG_E_DEVICE;
+    c->cur_i = c->cur_b = c->cur_e = c->cur_t = 0;
+    c->s = z;
+    c->s_valid = false;
+    return IG_OK;
+}
+
+ig_status ig_counts(ig_context* c, uint64_t* ni, uint64_t* nb, uint64_t* ne, uint64_t* nt) {
+    if (!c) return IG_E_INVALID;
+    const ig_status st = refresh(c);
+    if (st != IG_OK) return st;
+    if (ni) *ni = c->s.n_instr;
+    if (nb) *nb = c->s.n_binds;
+    if (ne) *ne = c->s.n_edges;
+    if (nt) *nt = c->s.n_tasks;
+    return IG_OK;
+}
+
+ig_status ig_fetch_instructions(ig_context* c, ig_instruction* dst, size_t cap, size_t* n_out) {
+    if (!c || (!dst && cap)) return IG_E_INVALID;
+    const ig_status st = refresh(c);
+    if (st != IG_OK) return st;
+    return fetch_records(c, c->s.n_instr, c->cur_i, dst, cap, n_out, [&](u64 first, u64 m, ig_instruction* out) {
+        return igrt::launch_pack_instructions(c->dctx, first, m, out, c->stream);
+    });
+}
+
+ig_status ig_fetch_bindings(ig_context* c, ig_binding* dst, size_t cap, size_t* n_out) {
+    if (!c || (!dst && cap)) return IG_E_INVALID;
+    const ig_status st = refresh(c);
+    if (st != IG_OK) return st;
+    return fetch_records(c, c->s.n_binds, c->cur_b, dst, cap, n_out, [&](u64 first, u64 m, ig_binding* out) {
+        return igrt::launch_pack_bindings(c->dctx, first, m, out, c->stream);
+    });
+}
+
+ig_status ig_fetch_edges(ig_context* c, ig_edge* dst, size_t cap, size_t* n_out) {
+    if (!c || (!dst && cap)) return IG_E_INVALID;
+    const ig_status st = refresh(c);
+    if (st != IG_OK) return st;
+    return fetch_records(c, c->s.n_edges, c->cur_e, dst, cap, n_out, [&](u64 first, u64 m, ig_edge* out) {
+        return igrt::launch_pack_edges(c->dctx, first, m, out, c->stream);
+    });
+}
+
+ig_status ig_fetch_task_status(ig_context* c, int32_t* dst, size_t cap, size_t* n_out) {
+    if (!c || (!dst && cap)) return IG_E_INVALID;
+    const ig_status st = refresh(c);
+    if (st != IG_OK) return st;
+    const u64 n = std::min<u64>(cap, c->s.n_tasks - c->cur_t);
+    if (n) {
+        if (igrt::copy_d2h(dst, c->h.task_status + c->cur_t, n * sizeof(int32_t), c->stream) != 0) return IG_E_DEVICE;
+        if (igrt::stream_sync(c->stream) != 0) return IG_E_DEVICE;
+    }
+    c->cur_t += n;
+    if (n_out) *n_out = (size_t)n;
+    return IG_OK;
+}
+
+ig_status ig_stats_get(ig_context* c, ig_stats* out) {
+    if (!c || !out) return IG_E_INVALID;
+    ig_status st = refresh(c);
+    if (st != IG_OK) return st;
+    if (igrt::memset_d(c->dstats, 0, sizeof(DevStats), c->stream) != 0) return IG_E_DEVICE;
+    if (igrt::launch_stats(c->dctx, c->s.n_instr, c->s.n_binds, c->s.n_edges, c->dstats, c->stream) != 0)
+        return IG_E_DEVICE;
+    DevStats ds;
+    if (igrt::copy_d2h(&ds, c->dstats, sizeof ds, c->stream) != 0) return IG_E_DEVICE;
+    if (igrt::stream_sync(c->stream) != 0) return IG_E_DEVICE;
+    std::memset(out, 0, sizeof *out);
+    out->n_instructions = c->s.n_instr;
+    out->n_bindings = c->s.n_binds;
+    out->n_edges = c->s.n_edges;
+    for (int i = 0; i < 8; ++i) out->per_kind[i] = ds.per_kind[i];
+    for (int i = 0; i < 5; ++i) out->per_dep[i] = ds.per_dep[i];
+    out->resizes = c->s.resizes;
+    out->warnings = c->s.warnings;
+    out->tasks_submitted = c->n_tasks;
+    out->tasks_rejected = c->s.rejected;
+    out->digest_instructions = ds.digest[0];
+    out->digest_bindings = ds.digest[1];
+    out->digest_edges = ds.digest[2];
+    out->commands_analysed = c->s.cmd_next;
+    out->launches = c->launches;
+    return IG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,295 @@
+// ig_dev.h -- device-side data layout of libig (instruction-graph generation).
+//
+// One stream (context) is analysed by ONE workgroup.  Its state lives in
+// device memory, described by DevCtx:
+//   * the recorded command log (buffer creation, tasks, epochs, destroys);
+//   * output records as structure-of-arrays (instructions, bindings, edges)
+//     plus one "has successor" byte per instruction (execution front);
+//   * per buffer a coordinate-compressed cell grid: the sorted coordinates at
+//     which any accessed region, allocation or buffer boundary starts or ends,
+//     per dimension.  Every region the analysis ever handles is a union of
+//     grid cells, so region maps are dense arrays over cells:
+//       buffer map   (per cell)  original producer, producer memory,
+//                                up-to-date memory mask        (Sec. 3.3)
+//       init map     (per cell)  initialised?                  (Sec. 4.4)
+//       allocation map (per cell of the allocation) last writer and the
+//                                head of a reader list          (Sec. 3.2)
+//     Grids are refined (cells split) when a task brings a new coordinate.
+//   * horizon/epoch substitution (Sec. 3.5) is applied lazily: an id below
+//     the current synchronisation point S reads as S, a reader below the last
+//     epoch E reads as absent; this equals rewriting every map eagerly.
+//
+// Work inside the workgroup is split by *memory*: the worker thread owning a
+// simulated memory performs every update of that memory's allocations, so
+// allocation maps need no atomics.  The one cross-memory effect (a coherence
+// copy reading a source allocation on another memory) is routed through a
+// per-memory inbox and applied by the owner after the copy phase.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ig.h"
+
+#ifdef IG_HOST_SIM
+// ---------------------------------------------------------------------------
+// Host emulation of one workgroup (test build only: std::threads + barrier).
+// The product library is always the HIP build; this exists so that the kernel
+// logic can be exercised and bounds-checked on a machine without a GPU.
+// ---------------------------------------------------------------------------
+#include <atomic>
+#include <cstring>
+#define __device__
+#define __host__
+#define __global__
+#define __forceinline__ inline
+namespace igsim {
+struct Barrier;
+struct ThreadCtx {
+    unsigned tid, nthreads, block;
+    Barrier* bar;
+};
+extern thread_local ThreadCtx cur;
+void barrier_wait(Barrier* b, int line);
+}  // namespace igsim
+inline unsigned ig_tid() { return igsim::cur.tid; }
+inline unsigned ig_nthreads() { return igsim::cur.nthreads; }
+inline unsigned ig_block() { return igsim::cur.block; }
+inline void ig_barrier_at(int line) { igsim::barrier_wait(igsim::cur.bar, line); }
+inline unsigned atomicAdd(unsigned* p, unsigned v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
+inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v) {
+    return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
+}
+inline unsigned long long atomicOr(unsigned long long* p, unsigned long long v) {
+    return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST);
+}
+inline unsigned atomicOr(unsigned* p, unsigned v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+inline unsigned atomicCAS(unsigned* p, unsigned cmp, unsigned v) {
+    __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
+    return cmp;
+}
+inline unsigned long long atomicCAS(unsigned long long* p, unsigned long long cmp, unsigned long long v) {
+    __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
+    return cmp;
+}
+inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+#define IGD inline
+#define IGN
+#else
+#include <hip/hip_runtime.h>
+__device__ __forceinline__ unsigned ig_tid() { return threadIdx.x; }
+__device__ __forceinline__ unsigned ig_nthreads() { return blockDim.x; }
+__device__ __forceinline__ unsigned ig_block() { return blockIdx.x; }
+__device__ __forceinline__ void ig_barrier_at(int) { __syncthreads(); }
+#define IGD __device__ __forceinline__
+#define IGN __device__ __noinline__
+#endif
+
+namespace igd {
+
+typedef uint8_t u8;
+typedef uint16_t u16;
+typedef uint32_t u32;
+typedef unsigned long long u64;
+typedef int64_t i64;
+typedef int32_t i32;
+
+constexpr u32 NONE = 0xFFFFFFFFu;
+constexpr u32 MAX_BUF = IG_MAX_BUFFERS;
+constexpr u32 MAX_LIVE = 16;   // live allocations per (buffer, memory)
+constexpr u32 MAX_PLAN = 16;   // planned boxes per (buffer, memory) while the queue is non-empty
+constexpr u32 MAX_THREADS = 1024;
+constexpr u32 MAX_CHUNKS = 4096;
+constexpr u32 RB_SLOTS = 7;    // reader ids per reader block (+1 word: next)
+
+enum CmdKind : u32 { CMD_BUFFER = 1, CMD_TASK = 2, CMD_EPOCH = 3, CMD_DESTROY = 4, CMD_SHUTDOWN = 5 };
+
+// One recorded command (host-written, device-read).
+struct DevCmd {
+    u32 kind;
+    u32 arg;        // buffer id (BUFFER, DESTROY) or task id (TASK)
+    u32 dims;       // BUFFER
+    u32 elem_size;  // BUFFER
+    u32 init;       // BUFFER
+    u32 pad[3];
+    i64 ext[3];       // BUFFER
+    ig_task_desc task;  // TASK
+};
+
+// Per-buffer grid and map arrays (offsets are word offsets into the heap).
+struct DBuf {
+    u32 alive, dims, init, user_alloc;
+    i64 ext[3];
+    u32 n[3];       // cells per dimension
+    u32 bp_off[3];  // i64[n[d]+1] breakpoints
+    u32 ncells;
+    u32 prod_off;   // u32[ncells]   original producer (NONE: uninitialised)
+    u32 pm_off;     // u32[ncells]   producer memory
+    u32 mask_off;   // u64[ncells*mw] up-to-date memories
+    u32 init_off;   // u32[ncells]   initialised (Sec. 4.4)
+    u32 stamp_off;  // u64[ncells]   overlapping-write detection: (task+1)<<32 | chunk
+    u32 pad;
+};
+
+struct DAlloc {
+    u32 buffer, mem, alive, ncells;
+    i64 lo[3], hi[3];   // allocation box (buffer coordinates)
+    u32 clo[3], chi[3]; // the same box in grid cells
+    u32 writer_off;     // u32[ncells] last writer
+    u32 rd_off;         // u32[ncells] reader-list heads
+};
+
+// One region of one (chunk, access) of the task being analysed.
+struct Region {
+    i64 lo[3], hi[3];
+    u32 clo[3], chi[3];
+    u32 buffer;
+    u32 mode;
+    u32 empty;
+    u32 pad;
+};
+
+// A coherence copy found in the counting pass.
+struct CopyRec {
+    u32 chunk, buffer, src_alloc, dst_alloc;
+    u32 src_mem, dst_mem, pad0, pad1;
+    u32 clo[3], chi[3];
+};
+
+// A read of a source allocation by a copy, routed to the owner of its memory.
+struct InboxRec {
+    u32 alloc, reader;
+    u32 clo[3], chi[3];
+};
+
+// Scalars persisted between launches (mirrored in LDS while a launch runs).
+struct Scalars {
+    u64 n_instr, n_edges, n_binds;
+    u64 warnings, rejected, resizes;
+    u32 cmd_next;        // next recorded command to analyse
+    u32 n_tasks;         // tasks analysed so far
+    u32 next_alloc;      // next allocation id
+    u32 S;               // synchronisation point: latest epoch or applied horizon
+    u32 E;               // latest epoch
+    u32 pending;         // emitted, not yet applied horizon (NONE)
+    u32 last_sync;       // latest horizon or epoch (the front starts there)
+    u32 tasks_since_sync;
+    u32 h;               // horizons queued since the last allocating command
+    u32 qlen;            // commands in the lookahead queue
+    u32 n_buffers;
+    u32 finished;
+    u32 heap_top;        // words
+    u32 rb_top;          // reader blocks
+    i32 error;
+    u32 pad;
+};
+
+struct DevCtx {
+    // --- configuration ---
+    u32 nodes, devices, chunks, per_dev, n_dev, n_mem, mw;
+    u32 horizon_step, lookahead, flush_horizons, queue_cap;
+    u32 threads, n_workers;
+    u32 cap_cmds, cap_allocs, cap_queue, cap_heap, cap_rb, cap_unit, cap_scr, cap_src, cap_box;
+    u32 pad0;
+    u64 cap_instr, cap_edges, cap_binds;
+    u32 cmd_end;  // commands recorded (set by the host before a launch)
+    u32 pad1;
+    // --- command log ---
+    DevCmd* cmds;
+    // --- outputs (structure of arrays) ---
+    u8* i_kind;
+    u8* i_flags;
+    u16* i_mem;
+    u16* i_src_mem;
+    u32* i_task;
+    u32* i_chunk;
+    u32* i_buffer;
+    u32* i_alloc;
+    u32* i_src_alloc;
+    i64* i_box;  // [6][cap_instr]: min0 min1 min2 max0 max1 max2
+    u32* e_from;
+    u32* e_to;
+    u8* e_kinds;
+    u32* b_instr;
+    u32* b_access;
+    u32* b_alloc;
+    u8* has_succ;
+    i32* task_status;
+    // --- state ---
+    DBuf* bufs;       // [MAX_BUF]
+    DAlloc* allocs;   // [cap_allocs]
+    u32* live_n;      // [MAX_BUF * n_mem]
+    u32* live;        // [MAX_BUF * n_mem * MAX_LIVE]
+    u32* plan_n;      // [MAX_BUF * n_mem]  NONE: not planned (use live)
+    i64* plan;        // [MAX_BUF * n_mem * MAX_PLAN * 6]
+    u32* queue;       // [cap_queue] command index, top bit: horizon
+    u32* heap;        // [cap_heap] words
+    u32* heap_free;   // [32] free-list heads per size class
+    u32* rb;          // [cap_rb * 8] reader blocks
+    u32* rb_free;     // [n_mem] free-list heads per memory
+    // --- per-command scratch ---
+    Region* reg;          // [MAX_CHUNKS * IG_MAX_ACCESS]
+    i64* chunk_lo;        // [MAX_CHUNKS]
+    i64* chunk_hi;        // [MAX_CHUNKS]
+    u32* cons_off;        // [MAX_CHUNKS * IG_MAX_ACCESS]
+    u32* cons_cnt;        // [MAX_CHUNKS * IG_MAX_ACCESS]
+    CopyRec* copies;      // [cap_unit]
+    u32* dev_cnt;         // [n_dev] copies per device, then kernels per device
+    u32* dev_base;        // [n_dev]
+    u32* kdev_cnt;        // [n_dev]
+    u32* kdev_base;       // [n_dev]
+    u32* inbox_cnt;       // [n_mem]
+    u32* inbox_off;       // [n_mem]
+    u32* inbox_cur;       // [n_mem]
+    InboxRec* inbox;      // [cap_unit]
+    u32* tab_off;         // [cap_unit] staged edges of each instruction of the unit
+    u32* tab_cnt;         // [cap_unit]
+    u32* stage_from;      // [cap_unit * 4]
+    u8* stage_kind;       // [cap_unit * 4]
+    u32* pair_flag;       // [MAX_BUF * n_mem] (allocation phase)
+    u32* pair_cnt;        // [MAX_BUF * n_mem]
+    u32* pair_acnt;       // [MAX_BUF * n_mem]
+    u32* miss_n;          // [1]
+    i64* miss_val;        // [cap_scr]
+    u32* miss_bd;         // [cap_scr] buffer*4+dim
+    u32* remap;           // [3 * cap_scr] old cell of new cell, per dim
+    // --- per-worker scratch ---
+    u64* wk_key;   // [n_workers * cap_scr]
+    u32* wk_val;   // [n_workers * cap_scr]
+    u64* wk_key2;  // [n_workers * cap_scr]
+    u32* wk_val2;  // [n_workers * cap_scr]
+    u64* wk_src;   // [n_workers * cap_src]
+    u64* wk_src2;  // [n_workers * cap_src]
+    i64* wk_box;   // [n_workers * cap_box * 6]
+    // --- persistent scalars ---
+    Scalars s;
+};
+
+// Per-launch results of the digest/statistics kernel.
+struct DevStats {
+    unsigned long long digest[3];
+    unsigned long long per_kind[8];
+    unsigned long long per_dep[5];
+};
+
+}  // namespace igd
+
+// Launch glue implemented next to the kernels (ig_kernels.hip).
+namespace igrt {
+int dev_malloc(void** p, size_t bytes);
+int dev_free(void* p);
+int host_malloc_pinned(void** p, size_t bytes);
+int host_free_pinned(void* p);
+int copy_h2d(void* dst, const void* src, size_t bytes, void* stream);
+int copy_d2h(void* dst, const void* src, size_t bytes, void* stream);
+int memset_d(void* dst, int v, size_t bytes, void* stream);
+int stream_sync(void* stream);
+int launch_analyse(igd::DevCtx* const* dev_ctx_ptrs_device, unsigned n_blocks, unsigned threads, void* stream);
+int launch_pack_instructions(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_instruction* out_dev,
+                             void* stream);
+int launch_pack_bindings(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_binding* out_dev, void* stream);
+int launch_pack_edges(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_edge* out_dev, void* stream);
+int launch_stats(const igd::DevCtx* dev_ctx, uint64_t n_instr, uint64_t n_bind, uint64_t n_edge,
+                 igd::DevStats* out_dev, void* stream);
+const char* last_error();
+}  // namespace igrt

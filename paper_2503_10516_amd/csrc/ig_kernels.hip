@@ -1,0 +1,2196 @@
+// ig_kernels.hip -- instruction-graph generation on gfx950.
+//
+// One workgroup analyses one stream (context); a launch may cover many
+// streams (one workgroup each).  Within a workgroup the control flow is
+// uniform: every thread walks the same command sequence, and the parallel
+// parts of each step are spread over the threads:
+//   * chunk split, range mappers, cell lookup, debug checks: over
+//     (chunk, access) pairs;
+//   * allocation phase, coherence copies, kernels, reader updates: over
+//     simulated memories -- the thread owning a memory does every update of
+//     that memory's allocation maps (no atomics needed there);
+//   * id/offset assignment: block-wide exclusive scans in LDS;
+//   * edge output: each instruction's sources are sorted, de-duplicated with
+//     their kinds OR-ed, staged, then written in (to, from) order after a
+//     scan of the per-instruction counts.
+// Paper passages: Sec. 3.1 (split), 3.2 (allocation), 3.3 (coherence),
+// 3.5 (horizons/epochs), Table 1 (instruction kinds), the dependency-kind
+// legend of the IDAG figure (Sec. 3.6), Sec. 4.1 (topological emission),
+// Sec. 4.3 (lookahead), Sec. 4.4 (debug checks).
+#include "ig_dev.h"
+
+namespace igd {
+
+// ===========================================================================
+// Workgroup-shared scratch (LDS)
+// ===========================================================================
+struct Shared {
+    Scalars s;
+    u32 scan[MAX_THREADS];
+    u32 scan_tmp[MAX_THREADS];
+    u32 total;
+    u32 flag;        // generic OR flag
+    u32 flag2;
+    u32 unit_first;  // first instruction id of the command being compiled
+    u32 unit_n;      // instructions of that command so far
+    u32 stage_top;   // staged edges of that command
+    u32 copy_top;    // coherence copies found for that task
+    u32 nfree;       // allocations freed in the allocation phase
+    u32 t_dims, t_nacc, t_id, t_cmd;
+    i64 t_lo[3], t_hi[3];
+    u32 n_alloc_instr, n_new_allocs, n_copies, n_kernels;
+    u32 win_first, win_n;  // lookahead window (queue positions)
+    u32 do_horizon;
+    u32 miss_total;
+};
+
+IGD u32 tid() { return ig_tid(); }
+IGD u32 nt() { return ig_nthreads(); }
+#define bar() ig_barrier_at(__LINE__)
+
+IGD void set_error(Shared& sh, i32 code) { atomicCAS((u32*)&sh.s.error, 0u, (u32)code); }
+
+// Uniform read of the error flag: every thread sees the same value because
+// nobody can set it between the two barriers.
+IGD bool failed(Shared& sh) {
+    bar();
+    const bool e = sh.s.error != 0;
+    bar();
+    return e;
+}
+
+// Uniform read of a word that threads may have just written (first barrier)
+// and that one thread may change right after (second barrier).
+IGD u32 uniform(const u32& v) {
+    bar();
+    const u32 x = v;
+    bar();
+    return x;
+}
+
+// ===========================================================================
+// Block-wide exclusive scan of a u32 array in global memory; returns total.
+// ===========================================================================
+IGN u32 block_exscan(Shared& sh, u32* a, u32 n) {
+    const u32 T = nt(), t = tid();
+    const u32 per = (n + T - 1) / T;
+    const u32 lo = t * per < n ? t * per : n;
+    const u32 hi = lo + per < n ? lo + per : n;
+    u32 sum = 0;
+    for (u32 i = lo; i < hi; ++i) sum += a[i];
+    sh.scan[t] = sum;
+    bar();
+    // Hillis-Steele inclusive scan over the per-thread sums
+    for (u32 off = 1; off < T; off <<= 1) {
+        u32 v = sh.scan[t];
+        if (t >= off) v += sh.scan[t - off];
+        bar();
+        sh.scan[t] = v;
+        bar();
+    }
+    const u32 incl = sh.scan[t];
+    if (t == T - 1) sh.total = incl;
+    u32 run = incl - sum;
+    for (u32 i = lo; i < hi; ++i) {
+        u32 v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    bar();
+    return sh.total;
+}
+
+// ===========================================================================
+// Heap: power-of-two blocks of 32-bit words for grids and map arrays.
+// Only thread 0 allocates and frees (between barriers).
+// ===========================================================================
+IGD u32 heap_alloc(DevCtx& c, Shared& sh, u32 words) {
+    u32 need = words + 2, k = 4;
+    while ((1u << k) < need) ++k;
+    u32 off;
+    if (c.heap_free[k]) {
+        off = c.heap_free[k];
+        c.heap_free[k] = c.heap[off + 2];
+    } else {
+        if ((u64)sh.s.heap_top + (1ull << k) > c.cap_heap) {
+            set_error(sh, IG_E_CAPACITY);
+            return 0;
+        }
+        off = sh.s.heap_top;
+        sh.s.heap_top += 1u << k;
+    }
+    c.heap[off] = k;
+    return off + 2;
+}
+
+IGD void heap_release(DevCtx& c, u32 p) {
+    if (!p) return;
+    const u32 off = p - 2, k = c.heap[off];
+    c.heap[off + 2] = c.heap_free[k];
+    c.heap_free[k] = off;
+}
+
+IGD u32* W32(DevCtx& c, u32 off) { return c.heap + off; }
+IGD u64* W64(DevCtx& c, u32 off) { return (u64*)(c.heap + off); }
+IGD i64* WI64(DevCtx& c, u32 off) { return (i64*)(c.heap + off); }
+
+// ===========================================================================
+// Reader lists: singly linked blocks of 7 ids; owned by one memory's worker.
+// ===========================================================================
+IGD u32 rb_alloc(DevCtx& c, Shared& sh, u32 m) {
+    u32 h = c.rb_free[m];
+    if (h) {
+        c.rb_free[m] = c.rb[h * 8 + 7];
+        return h;
+    }
+    u32 i = atomicAdd(&sh.s.rb_top, 1u);
+    if (i >= c.cap_rb) {
+        set_error(sh, IG_E_CAPACITY);
+        return 0;
+    }
+    return i;
+}
+
+IGD void rd_append(DevCtx& c, Shared& sh, u32 m, u32* head, u32 x) {
+    const u32 h = *head;
+    if (h) {
+        u32* blk = c.rb + h * 8;
+        for (u32 s = 0; s < RB_SLOTS; ++s)
+            if (blk[s] == NONE) {
+                blk[s] = x;
+                return;
+            }
+    }
+    const u32 n = rb_alloc(c, sh, m);
+    if (!n) return;
+    u32* blk = c.rb + n * 8;
+    blk[0] = x;
+    for (u32 s = 1; s < RB_SLOTS; ++s) blk[s] = NONE;
+    blk[7] = h;
+    *head = n;
+}
+
+IGD void rd_clear(DevCtx& c, u32 m, u32* head) {
+    u32 h = *head;
+    while (h) {
+        const u32 nx = c.rb[h * 8 + 7];
+        c.rb[h * 8 + 7] = c.rb_free[m];
+        c.rb_free[m] = h;
+        h = nx;
+    }
+    *head = 0;
+}
+
+IGN u32 rd_copy(DevCtx& c, Shared& sh, u32 m, u32 head) {
+    u32 out = 0;
+    for (u32 h = head; h; h = c.rb[h * 8 + 7])
+        for (u32 s = 0; s < RB_SLOTS; ++s)
+            if (c.rb[h * 8 + s] != NONE) rd_append(c, sh, m, &out, c.rb[h * 8 + s]);
+    return out;
+}
+
+// Lazy horizon/epoch substitution (Sec. 3.5): ids below the synchronisation
+// point read as S; readers from before the last epoch no longer exist.
+IGD u32 eff_w(const Shared& sh, u32 w) { return w < sh.s.S ? sh.s.S : w; }
+IGD bool eff_r(const Shared& sh, u32 r, u32& out) {
+    if (r < sh.s.E) return false;
+    out = r < sh.s.S ? sh.s.S : r;
+    return true;
+}
+
+// ===========================================================================
+// Per-thread source lists: (id << 8 | kind), sorted and de-duplicated.
+// ===========================================================================
+IGN void msort64(u64* a, u64* tmp, u32 n) {
+    u64* src = a;
+    u64* dst = tmp;
+    for (u32 w = 1; w < n; w <<= 1) {
+        for (u32 i = 0; i < n; i += 2 * w) {
+            u32 m = i + w < n ? i + w : n, e = i + 2 * w < n ? i + 2 * w : n;
+            u32 p = i, q = m, o = i;
+            while (p < m && q < e) dst[o++] = (src[q] < src[p]) ? src[q++] : src[p++];
+            while (p < m) dst[o++] = src[p++];
+            while (q < e) dst[o++] = src[q++];
+        }
+        u64* t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != a)
+        for (u32 i = 0; i < n; ++i) a[i] = src[i];
+}
+
+// stable sort of (key, val) pairs by key
+IGN void msort_kv(u64* k, u32* v, u64* k2, u32* v2, u32 n) {
+    u64* sk = k;
+    u32* sv = v;
+    u64* dk = k2;
+    u32* dv = v2;
+    for (u32 w = 1; w < n; w <<= 1) {
+        for (u32 i = 0; i < n; i += 2 * w) {
+            u32 m = i + w < n ? i + w : n, e = i + 2 * w < n ? i + 2 * w : n;
+            u32 p = i, q = m, o = i;
+            while (p < m && q < e) {
+                if (sk[q] < sk[p]) {
+                    dk[o] = sk[q];
+                    dv[o++] = sv[q++];
+                } else {
+                    dk[o] = sk[p];
+                    dv[o++] = sv[p++];
+                }
+            }
+            while (p < m) {
+                dk[o] = sk[p];
+                dv[o++] = sv[p++];
+            }
+            while (q < e) {
+                dk[o] = sk[q];
+                dv[o++] = sv[q++];
+            }
+        }
+        u64* tk = sk;
+        sk = dk;
+        dk = tk;
+        u32* tv = sv;
+        sv = dv;
+        dv = tv;
+    }
+    if (sk != k)
+        for (u32 i = 0; i < n; ++i) {
+            k[i] = sk[i];
+            v[i] = sv[i];
+        }
+}
+
+struct Src {
+    u64* buf;
+    u64* aux;
+    u32 n, cap;
+};
+
+IGN u32 src_dedup(Src& s) {
+    if (s.n == 0) return 0;
+    msort64(s.buf, s.aux, s.n);
+    u32 o = 0;
+    for (u32 i = 0; i < s.n; ++i) {
+        const u64 id = s.buf[i] >> 8;
+        if (o > 0 && (s.buf[o - 1] >> 8) == id)
+            s.buf[o - 1] |= s.buf[i] & 0xFF;
+        else
+            s.buf[o++] = s.buf[i];
+    }
+    s.n = o;
+    return o;
+}
+
+IGD void src_add(Shared& sh, Src& s, u32 id, u32 kind) {
+    if (s.n == s.cap) {
+        src_dedup(s);
+        if (s.n == s.cap) {
+            set_error(sh, IG_E_CAPACITY);
+            return;
+        }
+    }
+    s.buf[s.n++] = ((u64)id << 8) | kind;
+}
+
+IGD Src worker_src(DevCtx& c) {
+    Src s;
+    s.buf = c.wk_src + (size_t)tid() * c.cap_src;
+    s.aux = c.wk_src2 + (size_t)tid() * c.cap_src;
+    s.n = 0;
+    s.cap = c.cap_src;
+    return s;
+}
+
+// Stage the edges of instruction x (sources sorted by id, kinds OR-ed).  An
+// instruction without any dependency waits for the synchronisation point.
+IGN void stage(DevCtx& c, Shared& sh, u32 x, Src& s) {
+    if (s.n == 0) s.buf[s.n++] = ((u64)sh.s.S << 8) | IG_DEP_SYNC;
+    const u32 n = src_dedup(s);
+    const u32 off = atomicAdd(&sh.stage_top, n);
+    const u32 slot = x - sh.unit_first;
+    if ((u64)off + n > (u64)c.cap_unit * 8 || slot >= c.cap_unit) {
+        set_error(sh, IG_E_CAPACITY);
+        return;
+    }
+    for (u32 i = 0; i < n; ++i) {
+        const u32 from = (u32)(s.buf[i] >> 8);
+        c.stage_from[off + i] = from;
+        c.stage_kind[off + i] = (u8)(s.buf[i] & 0xFF);
+        c.has_succ[from] = 1;
+    }
+    c.tab_off[slot] = off;
+    c.tab_cnt[slot] = n;
+}
+
+// ===========================================================================
+// Instruction records
+// ===========================================================================
+IGD void put_instr(DevCtx& c, u32 x, u8 kind, u8 flags, u32 task, u32 chunk, u32 buffer, u32 mem, u32 src_mem,
+                   u32 alloc, u32 src_alloc, const i64 lo[3], const i64 hi[3]) {
+    c.i_kind[x] = kind;
+    c.i_flags[x] = flags;
+    c.i_mem[x] = (u16)mem;
+    c.i_src_mem[x] = (u16)src_mem;
+    c.i_task[x] = task;
+    c.i_chunk[x] = chunk;
+    c.i_buffer[x] = buffer;
+    c.i_alloc[x] = alloc;
+    c.i_src_alloc[x] = src_alloc;
+    const u64 cap = c.cap_instr;
+    for (u32 d = 0; d < 3; ++d) {
+        c.i_box[d * cap + x] = lo[d];
+        c.i_box[(3 + d) * cap + x] = hi[d];
+    }
+    c.has_succ[x] = 0;
+}
+
+// ===========================================================================
+// Grids and boxes
+// ===========================================================================
+IGD const i64* bps(DevCtx& c, const DBuf& B, u32 d) { return WI64(c, B.bp_off[d]); }
+
+IGD u32 bp_find(const i64* a, u32 n, i64 x) {  // exact index or NONE
+    u32 lo = 0, hi = n;
+    while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (a[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (lo < n && a[lo] == x) ? lo : NONE;
+}
+
+IGD u32 cell_of(const DBuf& B, u32 i0, u32 i1, u32 i2) { return (i0 * B.n[1] + i1) * B.n[2] + i2; }
+
+IGD u32 alloc_local(const DAlloc& a, u32 i0, u32 i1, u32 i2) {
+    return ((i0 - a.clo[0]) * (a.chi[1] - a.clo[1]) + (i1 - a.clo[1])) * (a.chi[2] - a.clo[2]) + (i2 - a.clo[2]);
+}
+
+IGD bool box_contains(const i64 olo[3], const i64 ohi[3], const i64 lo[3], const i64 hi[3]) {
+    for (u32 d = 0; d < 3; ++d)
+        if (lo[d] < olo[d] || hi[d] > ohi[d]) return false;
+    return true;
+}
+
+IGD bool box_empty(const i64 lo[3], const i64 hi[3]) {
+    for (u32 d = 0; d < 3; ++d)
+        if (lo[d] >= hi[d]) return true;
+    return false;
+}
+
+// merge relation of allocation planning: positive-volume overlap or a shared
+// face (touching in exactly one dimension, overlapping in the others)
+IGD bool box_merges(const i64* a, const i64* b) {
+    u32 pos = 0, touch = 0;
+    for (u32 d = 0; d < 3; ++d) {
+        const i64 hi = a[3 + d] < b[3 + d] ? a[3 + d] : b[3 + d];
+        const i64 lo = a[d] > b[d] ? a[d] : b[d];
+        const i64 ov = hi - lo;
+        if (ov > 0)
+            ++pos;
+        else if (ov == 0)
+            ++touch;
+    }
+    return pos == 3 || (pos == 2 && touch == 1);
+}
+
+IGD bool box6_contains(const i64* o, const i64* b) {
+    for (u32 d = 0; d < 3; ++d)
+        if (b[d] < o[d] || b[3 + d] > o[3 + d]) return false;
+    return true;
+}
+
+IGD bool box6_less(const i64* a, const i64* b) {
+    for (u32 d = 0; d < 6; ++d)
+        if (a[d] != b[d]) return a[d] < b[d];
+    return false;
+}
+
+// until no two boxes merge: replace merging pairs by their bounding box
+IGN u32 merge_fixpoint(i64* bx, u32 n) {
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        for (u32 i = 0; i < n; ++i) {
+            u32 j = i + 1;
+            while (j < n) {
+                i64* a = bx + 6 * i;
+                i64* b = bx + 6 * j;
+                if (box_merges(a, b)) {
+                    for (u32 d = 0; d < 3; ++d) {
+                        a[d] = a[d] < b[d] ? a[d] : b[d];
+                        a[3 + d] = a[3 + d] > b[3 + d] ? a[3 + d] : b[3 + d];
+                    }
+                    for (u32 d = 0; d < 6; ++d) b[d] = bx[6 * (n - 1) + d];
+                    --n;
+                    changed = true;
+                } else {
+                    ++j;
+                }
+            }
+        }
+    }
+    return n;
+}
+
+// Canonical decomposition of a sorted list of linear cell indices: dim-0
+// slabs cut where the 2-D cross-section changes, inside a slab dim-1 cut
+// where the 1-D cross-section changes, dim-2 maximal runs; boxes in order.
+template <class Emit>
+IGD u32 canon_cells(const u32* cells, u32 n, u32 n1, u32 n2, Emit emit) {
+    const u32 plane = n1 * n2;
+    u32 count = 0, p = 0;
+    while (p < n) {
+        const u32 i0 = cells[p] / plane;
+        u32 q = p;
+        while (q < n && cells[q] / plane == i0) ++q;
+        u32 i0b = i0 + 1, r = q;
+        while (r < n) {
+            const u32 j0 = cells[r] / plane;
+            if (j0 != i0b) break;
+            u32 s = r;
+            while (s < n && cells[s] / plane == j0) ++s;
+            if (s - r != q - p) break;
+            bool same = true;
+            for (u32 t = 0; t < q - p && same; ++t) same = (cells[p + t] % plane) == (cells[r + t] % plane);
+            if (!same) break;
+            ++i0b;
+            r = s;
+        }
+        u32 a = p;
+        while (a < q) {
+            const u32 i1 = (cells[a] % plane) / n2;
+            u32 b = a;
+            while (b < q && (cells[b] % plane) / n2 == i1) ++b;
+            u32 i1b = i1 + 1, cc = b;
+            while (cc < q) {
+                const u32 j1 = (cells[cc] % plane) / n2;
+                if (j1 != i1b) break;
+                u32 dd = cc;
+                while (dd < q && (cells[dd] % plane) / n2 == j1) ++dd;
+                if (dd - cc != b - a) break;
+                bool same = true;
+                for (u32 t = 0; t < b - a && same; ++t) same = (cells[a + t] % n2) == (cells[cc + t] % n2);
+                if (!same) break;
+                ++i1b;
+                cc = dd;
+            }
+            u32 e = a;
+            while (e < b) {
+                const u32 i2 = cells[e] % n2;
+                u32 f = e + 1;
+                while (f < b && cells[f] % n2 == cells[f - 1] % n2 + 1) ++f;
+                emit(i0, i0b, i1, i1b, i2, cells[f - 1] % n2 + 1);
+                ++count;
+                e = f;
+            }
+            a = cc;
+        }
+        p = r;
+    }
+    return count;
+}
+
+// ===========================================================================
+// Split (Sec. 3.1) and range mappers (Sec. 2.1, Listing 2)
+// ===========================================================================
+IGD i64 fpart(i64 n, i64 i, i64 parts) { return (n * i) / parts; }
+
+IGD void chunk_range(const DevCtx& c, i64 lo, i64 hi, u32 k, i64& clo, i64& chi) {
+    const u32 K = c.per_dev, dv = k / K, u = k % K, i = dv / c.devices, j = dv % c.devices;
+    const i64 n = hi - lo;
+    const i64 a = lo + fpart(n, i, c.nodes), b = lo + fpart(n, i + 1, c.nodes);
+    const i64 s = a + fpart(b - a, j, c.devices), e = a + fpart(b - a, j + 1, c.devices);
+    clo = s + fpart(e - s, u, K);
+    chi = s + fpart(e - s, u + 1, K);
+}
+
+IGD void map_region(const ig_access& a, const i64 clo[3], const i64 chi[3], const DBuf& B, i64 lo[3], i64 hi[3]) {
+    for (u32 d = 0; d < 3; ++d) {
+        lo[d] = 0;
+        hi[d] = 1;
+    }
+    for (u32 d = 0; d < B.dims; ++d) {
+        switch (a.mapper) {
+            case IG_MAP_ONE_TO_ONE:
+                lo[d] = clo[d];
+                hi[d] = chi[d];
+                break;
+            case IG_MAP_NEIGHBORHOOD:
+                lo[d] = clo[d] - a.radius[d];
+                hi[d] = chi[d] + a.radius[d];
+                break;
+            case IG_MAP_ALL:
+                lo[d] = 0;
+                hi[d] = B.ext[d];
+                break;
+            case IG_MAP_SLICE:
+                if (d == a.slice_dim) {
+                    lo[d] = 0;
+                    hi[d] = B.ext[d];
+                } else {
+                    lo[d] = clo[d];
+                    hi[d] = chi[d];
+                }
+                break;
+            default:
+                lo[d] = a.fixed.min[d];
+                hi[d] = a.fixed.max[d];
+                break;
+        }
+        if (lo[d] < 0) lo[d] = 0;
+        if (hi[d] > B.ext[d]) hi[d] = B.ext[d];
+    }
+}
+
+IGD u32 mem_of_chunk(const DevCtx& c, u32 k) { return 2 + k / c.per_dev; }
+IGD u32 owner_of(u32 m) { return m % nt(); }
+
+// live allocation on (b, m) containing a box (0: none)
+IGD u32 live_containing(DevCtx& c, u32 b, u32 m, const i64 lo[3], const i64 hi[3]) {
+    const u32 base = (b * c.n_mem + m) * MAX_LIVE, n = c.live_n[b * c.n_mem + m];
+    for (u32 i = 0; i < n; ++i) {
+        const DAlloc& a = c.allocs[c.live[base + i]];
+        if (box_contains(a.lo, a.hi, lo, hi)) return c.live[base + i];
+    }
+    return 0;
+}
+
+IGD u32 live_containing_cell(DevCtx& c, u32 b, u32 m, u32 i0, u32 i1, u32 i2) {
+    const u32 base = (b * c.n_mem + m) * MAX_LIVE, n = c.live_n[b * c.n_mem + m];
+    for (u32 i = 0; i < n; ++i) {
+        const DAlloc& a = c.allocs[c.live[base + i]];
+        if (i0 >= a.clo[0] && i0 < a.chi[0] && i1 >= a.clo[1] && i1 < a.chi[1] && i2 >= a.clo[2] && i2 < a.chi[2])
+            return c.live[base + i];
+    }
+    return 0;
+}
+
+// ===========================================================================
+// Regions of the current task: chunk ranges, mapped regions, grid cells.
+// Missing grid coordinates are collected for refinement.
+// ===========================================================================
+IGN void compute_regions(DevCtx& c, Shared& sh) {
+    const ig_task_desc& td = c.cmds[sh.t_cmd].task;
+    const u32 C = c.chunks, A = sh.t_nacc;
+    for (u32 k = tid(); k < C; k += nt()) chunk_range(c, sh.t_lo[0], sh.t_hi[0], k, c.chunk_lo[k], c.chunk_hi[k]);
+    bar();
+    for (u32 idx = tid(); idx < C * A; idx += nt()) {
+        const u32 k = idx / A, j = idx % A;
+        Region& r = c.reg[k * IG_MAX_ACCESS + j];
+        const ig_access& a = td.access[j];
+        r.buffer = a.buffer;
+        r.mode = a.mode;
+        i64 clo[3] = {c.chunk_lo[k], sh.t_lo[1], sh.t_lo[2]};
+        i64 chi[3] = {c.chunk_hi[k], sh.t_hi[1], sh.t_hi[2]};
+        r.empty = box_empty(clo, chi) ? 1u : 0u;
+        if (!r.empty) {
+            const DBuf& B = c.bufs[a.buffer];
+            map_region(a, clo, chi, B, r.lo, r.hi);
+            r.empty = box_empty(r.lo, r.hi) ? 1u : 0u;
+            if (!r.empty)
+                for (u32 d = 0; d < 3; ++d) {
+                    const i64* bp = bps(c, B, d);
+                    const u32 a0 = bp_find(bp, B.n[d] + 1, r.lo[d]);
+                    const u32 a1 = bp_find(bp, B.n[d] + 1, r.hi[d]);
+                    r.clo[d] = a0;
+                    r.chi[d] = a1;
+                    if (a0 == NONE || a1 == NONE) {
+                        const u32 slot = atomicAdd(c.miss_n, a0 == NONE && a1 == NONE ? 2u : 1u);
+                        u32 s = slot;
+                        if (a0 == NONE && s < c.cap_scr) {
+                            c.miss_val[s] = r.lo[d];
+                            c.miss_bd[s++] = a.buffer * 4 + d;
+                        } else if (a0 == NONE) {
+                            ++s;
+                        }
+                        if (a1 == NONE && s < c.cap_scr) {
+                            c.miss_val[s] = r.hi[d];
+                            c.miss_bd[s] = a.buffer * 4 + d;
+                        }
+                    }
+                }
+        }
+    }
+    bar();
+}
+
+// ===========================================================================
+// Grid refinement: insert new coordinates into a buffer's grid and move every
+// per-cell array of that buffer (buffer map, init, stamps, allocation maps)
+// onto the finer grid.  Values are copied, so the represented functions are
+// unchanged.
+// ===========================================================================
+IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u32 hi) {
+    DBuf& B = c.bufs[b];
+    // --- thread 0: new breakpoints, remap tables, new arrays ---
+    if (tid() == 0) {
+        u32 newoff[3], newn[3];
+        for (u32 d = 0; d < 3; ++d) {
+            const i64* old = bps(c, B, d);
+            const u32 no = B.n[d] + 1;
+            u32 cnt = 0;
+            for (u32 i = lo; i < hi; ++i)
+                if ((u32)(keys[i] >> 42) == b * 4 + d) ++cnt;
+            const u32 nn = no + cnt;
+            newoff[d] = heap_alloc(c, sh, 2 * nn);
+            if (sh.s.error) break;
+            i64* out = WI64(c, newoff[d]);
+            u32 p = 0, q = lo, o = 0;
+            while (q < hi && (u32)(keys[q] >> 42) != b * 4 + d) ++q;
+            while (p < no || (q < hi && (u32)(keys[q] >> 42) == b * 4 + d)) {
+                const bool take_new = q < hi && (u32)(keys[q] >> 42) == b * 4 + d &&
+                                      (p >= no || (i64)(keys[q] & ((1ull << 42) - 1)) < old[p]);
+                if (take_new)
+                    out[o++] = (i64)(keys[q++] & ((1ull << 42) - 1));
+                else
+                    out[o++] = old[p++];
+            }
+            newn[d] = o - 1;
+            if (newn[d] > c.cap_scr) {
+                set_error(sh, IG_E_CAPACITY);
+                break;
+            }
+            // old cell of each new cell
+            u32 oc = 0;
+            for (u32 i = 0; i < newn[d]; ++i) {
+                while (oc + 1 < no && old[oc + 1] <= out[i]) ++oc;
+                c.remap[d * c.cap_scr + i] = oc;
+            }
+        }
+        if (!sh.s.error) {
+            const u32 nc = newn[0] * newn[1] * newn[2];
+            sh.scan_tmp[0] = nc;
+            // stash old arrays in scan_tmp
+            sh.scan_tmp[1] = B.prod_off;
+            sh.scan_tmp[2] = B.pm_off;
+            sh.scan_tmp[3] = B.mask_off;
+            sh.scan_tmp[4] = B.init_off;
+            sh.scan_tmp[5] = B.stamp_off;
+            sh.scan_tmp[6] = B.n[0];
+            sh.scan_tmp[7] = B.n[1];
+            sh.scan_tmp[8] = B.n[2];
+            for (u32 d = 0; d < 3; ++d) {
+                heap_release(c, B.bp_off[d]);
+                B.bp_off[d] = newoff[d];
+                B.n[d] = newn[d];
+            }
+            B.ncells = nc;
+            B.prod_off = heap_alloc(c, sh, nc);
+            B.pm_off = heap_alloc(c, sh, nc);
+            B.mask_off = heap_alloc(c, sh, 2 * nc * c.mw);
+            B.init_off = heap_alloc(c, sh, nc);
+            B.stamp_off = heap_alloc(c, sh, 2 * nc);
+            // allocations of this buffer: new cell boxes and arrays
+            u32 na = 0;
+            for (u32 m = 0; m < c.n_mem; ++m) {
+                const u32 base = (b * c.n_mem + m) * MAX_LIVE, n = c.live_n[b * c.n_mem + m];
+                for (u32 i = 0; i < n; ++i) {
+                    DAlloc& a = c.allocs[c.live[base + i]];
+                    c.cons_off[na++] = c.live[base + i];
+                    // old geometry goes to the region scratch of this slot
+                    Region& sv = c.reg[na - 1];
+                    for (u32 d = 0; d < 3; ++d) {
+                        sv.clo[d] = a.clo[d];
+                        sv.chi[d] = a.chi[d];
+                        a.clo[d] = bp_find(bps(c, B, d), B.n[d] + 1, a.lo[d]);
+                        a.chi[d] = bp_find(bps(c, B, d), B.n[d] + 1, a.hi[d]);
+                    }
+                    sv.buffer = a.writer_off;
+                    sv.mode = a.rd_off;
+                    a.ncells = (a.chi[0] - a.clo[0]) * (a.chi[1] - a.clo[1]) * (a.chi[2] - a.clo[2]);
+                    a.writer_off = heap_alloc(c, sh, a.ncells);
+                    a.rd_off = heap_alloc(c, sh, a.ncells);
+                }
+            }
+            sh.scan_tmp[9] = na;
+        }
+    }
+    if (failed(sh)) return;
+    const u32 nc = sh.scan_tmp[0];
+    const u32 on1 = sh.scan_tmp[7], on2 = sh.scan_tmp[8];
+    const u32* r0 = c.remap;
+    const u32* r1 = c.remap + c.cap_scr;
+    const u32* r2 = c.remap + 2 * c.cap_scr;
+    // --- buffer-level arrays ---
+    for (u32 cell = tid(); cell < nc; cell += nt()) {
+        const u32 i2 = cell % B.n[2], i1 = (cell / B.n[2]) % B.n[1], i0 = cell / (B.n[1] * B.n[2]);
+        const u32 oc = (r0[i0] * on1 + r1[i1]) * on2 + r2[i2];
+        W32(c, B.prod_off)[cell] = W32(c, sh.scan_tmp[1])[oc];
+        W32(c, B.pm_off)[cell] = W32(c, sh.scan_tmp[2])[oc];
+        for (u32 w = 0; w < c.mw; ++w) W64(c, B.mask_off)[cell * c.mw + w] = W64(c, sh.scan_tmp[3])[oc * c.mw + w];
+        W32(c, B.init_off)[cell] = W32(c, sh.scan_tmp[4])[oc];
+        W64(c, B.stamp_off)[cell] = W64(c, sh.scan_tmp[5])[oc];
+    }
+    // --- allocation maps: each by the owner of its memory ---
+    const u32 na = sh.scan_tmp[9];
+    for (u32 s = 0; s < na; ++s) {
+        const u32 id = c.cons_off[s];
+        DAlloc& a = c.allocs[id];
+        if (owner_of(a.mem) != tid()) continue;
+        const Region& sv = c.reg[s];
+        const u32 on1a = sv.chi[1] - sv.clo[1], on2a = sv.chi[2] - sv.clo[2];
+        u32* wr = W32(c, a.writer_off);
+        u32* rd = W32(c, a.rd_off);
+        const u32* owr = W32(c, sv.buffer);
+        const u32* ord = W32(c, sv.mode);
+        u32 l = 0;
+        for (u32 i0 = a.clo[0]; i0 < a.chi[0]; ++i0)
+            for (u32 i1 = a.clo[1]; i1 < a.chi[1]; ++i1)
+                for (u32 i2 = a.clo[2]; i2 < a.chi[2]; ++i2, ++l) {
+                    const u32 ol = ((r0[i0] - sv.clo[0]) * on1a + (r1[i1] - sv.clo[1])) * on2a + (r2[i2] - sv.clo[2]);
+                    wr[l] = owr[ol];
+                    rd[l] = rd_copy(c, sh, a.mem, ord[ol]);
+                }
+        const u32 ocells = (sv.chi[0] - sv.clo[0]) * on1a * on2a;
+        for (u32 ol = 0; ol < ocells; ++ol) {
+            u32 h = ord[ol];
+            rd_clear(c, a.mem, &h);
+        }
+    }
+    bar();
+    if (tid() == 0) {
+        for (u32 s = 1; s <= 5; ++s) heap_release(c, sh.scan_tmp[s]);
+        for (u32 s = 0; s < na; ++s) {
+            heap_release(c, c.reg[s].buffer);
+            heap_release(c, c.reg[s].mode);
+        }
+    }
+    bar();
+}
+
+IGN void refine_all(DevCtx& c, Shared& sh) {
+    // thread 0 sorts the missing coordinates (key = buffer*4+dim, value)
+    if (tid() == 0) {
+        u32 n = *c.miss_n;
+        if (n > c.cap_scr) {
+            set_error(sh, IG_E_CAPACITY);
+            n = 0;
+        }
+        u64* key = c.wk_key;
+        for (u32 i = 0; i < n; ++i) key[i] = ((u64)c.miss_bd[i] << 42) | (u64)c.miss_val[i];
+        msort64(key, c.wk_key2, n);
+        u32 o = 0;
+        for (u32 i = 0; i < n; ++i)
+            if (o == 0 || key[o - 1] != key[i]) key[o++] = key[i];
+        sh.miss_total = o;
+        *c.miss_n = 0;
+    }
+    bar();
+    const u32 n = uniform(sh.miss_total);
+    u32 i = 0;
+    while (i < n && !failed(sh)) {
+        const u32 b = (u32)(c.wk_key[i] >> 44);
+        u32 j = i;
+        while (j < n && (u32)(c.wk_key[j] >> 44) == b) ++j;
+        refine_buffer(c, sh, b, c.wk_key, i, j);
+        i = j;
+    }
+    bar();
+}
+
+// ===========================================================================
+// Output of a compiled command: staged edges -> edge records in (to, from)
+// order.
+// ===========================================================================
+IGD void unit_begin(DevCtx& c, Shared& sh) {
+    if (tid() == 0) {
+        sh.unit_first = (u32)sh.s.n_instr;
+        sh.unit_n = 0;
+        sh.stage_top = 0;
+        sh.copy_top = 0;
+        sh.nfree = 0;
+    }
+    bar();
+}
+
+IGN void unit_end(DevCtx& c, Shared& sh) {
+    if (failed(sh)) return;
+    const u32 n = sh.unit_n;
+    // per-instruction edge counts -> output offsets
+    const u32 total = block_exscan(sh, c.tab_cnt, n);
+    if ((u64)sh.s.n_edges + total > c.cap_edges) {
+        if (tid() == 0) set_error(sh, IG_E_CAPACITY);
+        bar();
+        return;
+    }
+    const u64 base = sh.s.n_edges;
+    for (u32 i = tid(); i < n; i += nt()) {
+        const u32 off = c.tab_cnt[i];
+        const u32 cnt = (i + 1 < n ? c.tab_cnt[i + 1] : total) - off;
+        const u32 src = c.tab_off[i];
+        for (u32 e = 0; e < cnt; ++e) {
+            c.e_from[base + off + e] = c.stage_from[src + e];
+            c.e_kinds[base + off + e] = c.stage_kind[src + e];
+            c.e_to[base + off + e] = sh.unit_first + i;
+        }
+    }
+    bar();
+    if (tid() == 0) {
+        sh.s.n_edges += total;
+        sh.s.n_instr += n;
+    }
+    bar();
+}
+
+// ===========================================================================
+// Horizons and epochs (Sec. 3.5): SYNC edges from the execution front, i.e.
+// every instruction since the last horizon/epoch without a successor.
+// ===========================================================================
+IGN void compile_sync(DevCtx& c, Shared& sh, bool epoch) {
+    if ((u64)sh.s.n_instr + 1 > c.cap_instr) {
+        if (tid() == 0) set_error(sh, IG_E_CAPACITY);
+        bar();
+        return;
+    }
+    const u32 x = (u32)sh.s.n_instr;
+    const u32 lo = sh.s.last_sync, n = x - lo;
+    const u32 T = nt(), t = tid(), per = (n + T - 1) / T;
+    const u32 a = lo + (t * per < n ? t * per : n), e = (a + per < x) ? a + per : x;
+    u32 cnt = 0;
+    for (u32 i = a; i < e; ++i) cnt += c.has_succ[i] ? 0 : 1;
+    sh.scan[t] = cnt;
+    bar();
+    for (u32 off = 1; off < T; off <<= 1) {
+        u32 v = sh.scan[t];
+        if (t >= off) v += sh.scan[t - off];
+        bar();
+        sh.scan[t] = v;
+        bar();
+    }
+    if (t == T - 1) sh.total = sh.scan[t];
+    bar();
+    const u32 total = sh.total;
+    if ((u64)sh.s.n_edges + total > c.cap_edges) {
+        if (t == 0) set_error(sh, IG_E_CAPACITY);
+        bar();
+        return;
+    }
+    u64 o = sh.s.n_edges + sh.scan[t] - cnt;
+    for (u32 i = a; i < e; ++i)
+        if (!c.has_succ[i]) {
+            c.e_from[o] = i;
+            c.e_to[o] = x;
+            c.e_kinds[o] = IG_DEP_SYNC;
+            ++o;
+            c.has_succ[i] = 1;
+        }
+    bar();
+    if (t == 0) {
+        const i64 z[3] = {0, 0, 0};
+        put_instr(c, x, epoch ? IG_EPOCH : IG_HORIZON, 0, NONE, NONE, NONE, 0xFFFF, 0xFFFF, 0, 0, z, z);
+        sh.s.n_edges += total;
+        sh.s.n_instr += 1;
+        if (epoch) {
+            sh.s.E = x;
+            sh.s.S = x;
+            sh.s.pending = NONE;
+        } else {
+            if (sh.s.pending != NONE) sh.s.S = sh.s.pending;
+            sh.s.pending = x;
+        }
+        sh.s.last_sync = x;
+    }
+    bar();
+}
+
+// ===========================================================================
+// Allocation phase (Sec. 3.2).  Per (buffer, memory) whose requirements of
+// this task are not all inside a live allocation: merge the live allocations
+// with all window requirements on that pair, allocate each resulting box that
+// holds an uncovered requirement, copy the up-to-date data of every swallowed
+// allocation into it (resize), free the swallowed ones.
+// ===========================================================================
+
+// Boxes of the pair (b, m): live allocations and window requirements;
+// returns the number of merged boxes in the worker's box scratch, with the
+// new ones (holding an uncovered requirement of this task) first, sorted.
+IGN u32 plan_pair(DevCtx& c, Shared& sh, u32 b, u32 m, u32& n_new) {
+    i64* bx = c.wk_box + (size_t)tid() * c.cap_box * 6;
+    u32 n = 0;
+    const u32 lb = (b * c.n_mem + m) * MAX_LIVE, ln = c.live_n[b * c.n_mem + m];
+    auto add = [&](const i64* lo, const i64* hi) {
+        for (u32 i = 0; i < n; ++i) {
+            const i64* q = bx + 6 * i;
+            if (q[0] == lo[0] && q[1] == lo[1] && q[2] == lo[2] && q[3] == hi[0] && q[4] == hi[1] && q[5] == hi[2])
+                return;
+        }
+        if (n >= c.cap_box) {
+            set_error(sh, IG_E_CAPACITY);
+            return;
+        }
+        i64* q = bx + 6 * n++;
+        for (u32 d = 0; d < 3; ++d) {
+            q[d] = lo[d];
+            q[3 + d] = hi[d];
+        }
+    };
+    for (u32 i = 0; i < ln; ++i) {
+        const DAlloc& a = c.allocs[c.live[lb + i]];
+        add(a.lo, a.hi);
+    }
+    const u32 d = m - 2, A = sh.t_nacc;
+    for (u32 k = d * c.per_dev; k < (d + 1) * c.per_dev; ++k)
+        for (u32 j = 0; j < A; ++j) {
+            const Region& r = c.reg[k * IG_MAX_ACCESS + j];
+            if (!r.empty && r.buffer == b) add(r.lo, r.hi);
+        }
+    // the commands queued behind this task in the current flush
+    for (u32 w = 0; w < sh.win_n; ++w) {
+        const u32 e = c.queue[sh.win_first + w];
+        if (e & 0x80000000u) continue;
+        const ig_task_desc& td = c.cmds[e].task;
+        for (u32 k = d * c.per_dev; k < (d + 1) * c.per_dev; ++k) {
+            i64 clo[3], chi[3];
+            chunk_range(c, td.box.min[0], td.box.max[0], k, clo[0], chi[0]);
+            clo[1] = td.box.min[1];
+            clo[2] = td.box.min[2];
+            chi[1] = td.box.max[1];
+            chi[2] = td.box.max[2];
+            if (box_empty(clo, chi)) continue;
+            for (u32 j = 0; j < td.n_access; ++j) {
+                if (td.access[j].buffer != b) continue;
+                i64 lo[3], hi[3];
+                map_region(td.access[j], clo, chi, c.bufs[b], lo, hi);
+                if (!box_empty(lo, hi)) add(lo, hi);
+            }
+        }
+    }
+    n = merge_fixpoint(bx, n);
+    // new boxes: those containing an uncovered requirement of this task
+    u32 nn = 0;
+    for (u32 i = 0; i < n; ++i) {
+        bool hit = false;
+        for (u32 k = d * c.per_dev; k < (d + 1) * c.per_dev && !hit; ++k)
+            for (u32 j = 0; j < A && !hit; ++j) {
+                const Region& r = c.reg[k * IG_MAX_ACCESS + j];
+                if (r.empty || r.buffer != b) continue;
+                i64 rb6[6] = {r.lo[0], r.lo[1], r.lo[2], r.hi[0], r.hi[1], r.hi[2]};
+                if (!box6_contains(bx + 6 * i, rb6)) continue;
+                if (live_containing(c, b, m, r.lo, r.hi) == 0) hit = true;
+            }
+        if (hit) {
+            for (u32 t = 0; t < 6; ++t) {
+                const i64 v = bx[6 * nn + t];
+                bx[6 * nn + t] = bx[6 * i + t];
+                bx[6 * i + t] = v;
+            }
+            ++nn;
+        }
+    }
+    // insertion sort of the new boxes by their minimum (lexicographic)
+    for (u32 i = 1; i < nn; ++i)
+        for (u32 j = i; j > 0 && box6_less(bx + 6 * j, bx + 6 * (j - 1)); --j)
+            for (u32 t = 0; t < 6; ++t) {
+                const i64 v = bx[6 * j + t];
+                bx[6 * j + t] = bx[6 * (j - 1) + t];
+                bx[6 * (j - 1) + t] = v;
+            }
+    n_new = nn;
+    return n;
+}
+
+// cells of allocation `a` that are up to date on memory m, sorted
+IGN u32 utd_cells(DevCtx& c, Shared& sh, const DAlloc& a, u32 m, u32* out) {
+    const DBuf& B = c.bufs[a.buffer];
+    const u64* mask = W64(c, B.mask_off);
+    u32 n = 0;
+    for (u32 i0 = a.clo[0]; i0 < a.chi[0]; ++i0)
+        for (u32 i1 = a.clo[1]; i1 < a.chi[1]; ++i1)
+            for (u32 i2 = a.clo[2]; i2 < a.chi[2]; ++i2) {
+                const u32 cell = cell_of(B, i0, i1, i2);
+                if ((mask[cell * c.mw + (m >> 6)] >> (m & 63)) & 1) {
+                    if (n >= c.cap_scr) {
+                        set_error(sh, IG_E_CAPACITY);
+                        return n;
+                    }
+                    out[n++] = cell;
+                }
+            }
+    return n;
+}
+
+// sorted ids of the live allocations of (b, m) inside box q
+IGD u32 absorbed_of(DevCtx& c, u32 b, u32 m, const i64* q, u32* out) {
+    const u32 lb = (b * c.n_mem + m) * MAX_LIVE, ln = c.live_n[b * c.n_mem + m];
+    u32 n = 0;
+    for (u32 i = 0; i < ln; ++i) {
+        const DAlloc& a = c.allocs[c.live[lb + i]];
+        const i64 ab[6] = {a.lo[0], a.lo[1], a.lo[2], a.hi[0], a.hi[1], a.hi[2]};
+        if (box6_contains(q, ab)) out[n++] = c.live[lb + i];
+    }
+    for (u32 i = 1; i < n; ++i)
+        for (u32 j = i; j > 0 && out[j] < out[j - 1]; --j) {
+            const u32 v = out[j];
+            out[j] = out[j - 1];
+            out[j - 1] = v;
+        }
+    return n;
+}
+
+// access edges of one instruction against an allocation map, per cell
+IGD void edges_read(DevCtx& c, Shared& sh, Src& s, const DAlloc& a, u32 l) {
+    const u32 w = eff_w(sh, W32(c, a.writer_off)[l]);
+    src_add(sh, s, w, c.i_kind[w] == IG_ALLOC ? IG_DEP_LIFETIME : IG_DEP_TRUE);
+}
+
+IGN void edges_write(DevCtx& c, Shared& sh, Src& s, const DAlloc& a, u32 l) {
+    bool any = false;
+    for (u32 h = W32(c, a.rd_off)[l]; h; h = c.rb[h * 8 + 7])
+        for (u32 q = 0; q < RB_SLOTS; ++q) {
+            const u32 r = c.rb[h * 8 + q];
+            u32 e;
+            if (r != NONE && eff_r(sh, r, e)) {
+                src_add(sh, s, e, IG_DEP_ANTI);
+                any = true;
+            }
+        }
+    if (!any) {
+        const u32 w = eff_w(sh, W32(c, a.writer_off)[l]);
+        src_add(sh, s, w, c.i_kind[w] == IG_ALLOC ? IG_DEP_LIFETIME : IG_DEP_OUTPUT);
+    }
+}
+
+IGN void free_edges(DevCtx& c, Shared& sh, Src& s, const DAlloc& a) {
+    for (u32 l = 0; l < a.ncells; ++l) {
+        src_add(sh, s, eff_w(sh, W32(c, a.writer_off)[l]), IG_DEP_LIFETIME);
+        for (u32 h = W32(c, a.rd_off)[l]; h; h = c.rb[h * 8 + 7])
+            for (u32 q = 0; q < RB_SLOTS; ++q) {
+                const u32 r = c.rb[h * 8 + q];
+                u32 e;
+                if (r != NONE && eff_r(sh, r, e)) src_add(sh, s, e, IG_DEP_LIFETIME);
+            }
+    }
+}
+
+IGN void release_readers(DevCtx& c, const DAlloc& a) {
+    u32* rd = W32(c, a.rd_off);
+    for (u32 l = 0; l < a.ncells; ++l) rd_clear(c, a.mem, &rd[l]);
+}
+
+IGD void live_remove(DevCtx& c, u32 b, u32 m, u32 id) {
+    const u32 lb = (b * c.n_mem + m) * MAX_LIVE;
+    u32& ln = c.live_n[b * c.n_mem + m];
+    for (u32 i = 0; i < ln; ++i)
+        if (c.live[lb + i] == id) {
+            c.live[lb + i] = c.live[lb + ln - 1];
+            --ln;
+            return;
+        }
+}
+
+IGN void alloc_phase(DevCtx& c, Shared& sh) {
+    const u32 NP = sh.s.n_buffers * c.n_mem, A = sh.t_nacc, C = c.chunks;
+    for (u32 i = tid(); i < NP; i += nt()) {
+        c.pair_flag[i] = 0;
+        c.pair_cnt[i] = 0;
+        c.pair_acnt[i] = 0;
+    }
+    if (tid() == 0) sh.flag = 0;
+    bar();
+    for (u32 idx = tid(); idx < C * A; idx += nt()) {
+        const u32 k = idx / A, j = idx % A;
+        const Region& r = c.reg[k * IG_MAX_ACCESS + j];
+        if (r.empty) continue;
+        const u32 m = mem_of_chunk(c, k);
+        if (live_containing(c, r.buffer, m, r.lo, r.hi) == 0) {
+            c.pair_flag[r.buffer * c.n_mem + m] = 1;
+            sh.flag = 1;
+        }
+    }
+    if (!uniform(sh.flag)) {
+        if (tid() == 0) sh.n_alloc_instr = 0;
+        bar();
+        return;
+    }
+    // counting pass, per memory worker
+    u32* absorb = c.wk_val + (size_t)tid() * c.cap_scr;
+    u32* cells = c.wk_val2 + (size_t)tid() * c.cap_scr;
+    const i64* bx = c.wk_box + (size_t)tid() * c.cap_box * 6;
+    for (u32 m = tid(); m < c.n_mem; m += nt()) {
+        if (m < 2) continue;
+        for (u32 b = 0; b < sh.s.n_buffers; ++b) {
+            if (!c.pair_flag[b * c.n_mem + m]) continue;
+            u32 nn;
+            plan_pair(c, sh, b, m, nn);
+            u32 cnt = 0;
+            for (u32 i = 0; i < nn; ++i) {
+                const u32 na = absorbed_of(c, b, m, bx + 6 * i, absorb);
+                cnt += 1 + na;
+                for (u32 q = 0; q < na; ++q) {
+                    const u32 nc = utd_cells(c, sh, c.allocs[absorb[q]], m, cells);
+                    cnt += canon_cells(cells, nc, c.bufs[b].n[1], c.bufs[b].n[2],
+                                       [](u32, u32, u32, u32, u32, u32) {});
+                }
+            }
+            c.pair_cnt[b * c.n_mem + m] = cnt;
+            c.pair_acnt[b * c.n_mem + m] = nn;
+        }
+    }
+    bar();
+    const u32 total = block_exscan(sh, c.pair_cnt, NP);
+    const u32 total_allocs = block_exscan(sh, c.pair_acnt, NP);
+    if (tid() == 0) {
+        if (sh.unit_first + total > c.cap_instr || sh.s.next_alloc + total_allocs > c.cap_allocs || total > c.cap_unit)
+            set_error(sh, IG_E_CAPACITY);
+    }
+    if (failed(sh)) return;
+    // the new allocations' geometry -> thread 0 creates their map arrays
+    for (u32 m = tid(); m < c.n_mem; m += nt()) {
+        if (m < 2) continue;
+        for (u32 b = 0; b < sh.s.n_buffers; ++b) {
+            if (!c.pair_flag[b * c.n_mem + m]) continue;
+            u32 nn;
+            plan_pair(c, sh, b, m, nn);
+            for (u32 i = 0; i < nn; ++i) {
+                DAlloc& na = c.allocs[sh.s.next_alloc + c.pair_acnt[b * c.n_mem + m] + i];
+                const DBuf& B = c.bufs[b];
+                na.buffer = b;
+                na.mem = m;
+                na.alive = 1;
+                for (u32 d = 0; d < 3; ++d) {
+                    na.lo[d] = bx[6 * i + d];
+                    na.hi[d] = bx[6 * i + 3 + d];
+                    na.clo[d] = bp_find(bps(c, B, d), B.n[d] + 1, na.lo[d]);
+                    na.chi[d] = bp_find(bps(c, B, d), B.n[d] + 1, na.hi[d]);
+                }
+                na.ncells = (na.chi[0] - na.clo[0]) * (na.chi[1] - na.clo[1]) * (na.chi[2] - na.clo[2]);
+            }
+        }
+    }
+    bar();
+    if (tid() == 0) {
+        for (u32 i = 0; i < total_allocs; ++i) {
+            DAlloc& na = c.allocs[sh.s.next_alloc + i];
+            na.writer_off = heap_alloc(c, sh, na.ncells);
+            na.rd_off = heap_alloc(c, sh, na.ncells);
+        }
+    }
+    if (failed(sh)) return;
+    // emission pass
+    for (u32 m = tid(); m < c.n_mem; m += nt()) {
+        if (m < 2) continue;
+        for (u32 b = 0; b < sh.s.n_buffers; ++b) {
+            if (!c.pair_flag[b * c.n_mem + m]) continue;
+            u32 nn;
+            plan_pair(c, sh, b, m, nn);
+            u32 x = sh.unit_first + c.pair_cnt[b * c.n_mem + m];
+            const DBuf& B = c.bufs[b];
+            for (u32 i = 0; i < nn; ++i) {
+                const u32 nid = sh.s.next_alloc + c.pair_acnt[b * c.n_mem + m] + i;
+                DAlloc& na = c.allocs[nid];
+                const u32 xa = x++;
+                put_instr(c, xa, IG_ALLOC, 0, sh.t_id, NONE, b, m, 0xFFFF, nid, 0, na.lo, na.hi);
+                Src s0 = worker_src(c);
+                stage(c, sh, xa, s0);
+                u32* wr = W32(c, na.writer_off);
+                u32* rd = W32(c, na.rd_off);
+                for (u32 l = 0; l < na.ncells; ++l) {
+                    wr[l] = xa;
+                    rd[l] = 0;
+                }
+                const u32 nabs = absorbed_of(c, b, m, bx + 6 * i, absorb);
+                for (u32 q = 0; q < nabs; ++q) {
+                    const DAlloc& old = c.allocs[absorb[q]];
+                    const u32 nc = utd_cells(c, sh, old, m, cells);
+                    canon_cells(cells, nc, B.n[1], B.n[2], [&](u32 a0, u32 a1, u32 b0, u32 b1, u32 c0, u32 c1) {
+                        const u32 xc = x++;
+                        i64 lo[3] = {bps(c, B, 0)[a0], bps(c, B, 1)[b0], bps(c, B, 2)[c0]};
+                        i64 hi[3] = {bps(c, B, 0)[a1], bps(c, B, 1)[b1], bps(c, B, 2)[c1]};
+                        put_instr(c, xc, IG_COPY, IG_F_RESIZE, sh.t_id, NONE, b, m, m, nid, absorb[q], lo, hi);
+                        Src s = worker_src(c);
+                        for (u32 i0 = a0; i0 < a1; ++i0)
+                            for (u32 i1 = b0; i1 < b1; ++i1)
+                                for (u32 i2 = c0; i2 < c1; ++i2) {
+                                    edges_read(c, sh, s, old, alloc_local(old, i0, i1, i2));
+                                    edges_write(c, sh, s, na, alloc_local(na, i0, i1, i2));
+                                }
+                        stage(c, sh, xc, s);
+                        for (u32 i0 = a0; i0 < a1; ++i0)
+                            for (u32 i1 = b0; i1 < b1; ++i1)
+                                for (u32 i2 = c0; i2 < c1; ++i2) {
+                                    const u32 lo_ = alloc_local(old, i0, i1, i2);
+                                    rd_append(c, sh, m, &W32(c, old.rd_off)[lo_], xc);
+                                    const u32 ln = alloc_local(na, i0, i1, i2);
+                                    wr[ln] = xc;
+                                    rd_clear(c, m, &rd[ln]);
+                                }
+                    });
+                }
+                for (u32 q = 0; q < nabs; ++q) {
+                    DAlloc& old = c.allocs[absorb[q]];
+                    const u32 xf = x++;
+                    put_instr(c, xf, IG_FREE, 0, sh.t_id, NONE, b, m, 0xFFFF, absorb[q], 0, old.lo, old.hi);
+                    Src s = worker_src(c);
+                    free_edges(c, sh, s, old);
+                    stage(c, sh, xf, s);
+                    release_readers(c, old);
+                    old.alive = 0;
+                    live_remove(c, b, m, absorb[q]);
+                    const u32 slot = atomicAdd(&sh.nfree, 1u);
+                    c.miss_bd[slot] = absorb[q];  // freed: arrays released below
+                }
+                const u32 lb = (b * c.n_mem + m) * MAX_LIVE;
+                u32& ln = c.live_n[b * c.n_mem + m];
+                if (ln >= MAX_LIVE) {
+                    set_error(sh, IG_E_CAPACITY);
+                } else {
+                    c.live[lb + ln] = nid;
+                    ++ln;
+                }
+            }
+        }
+    }
+    bar();
+    if (tid() == 0) {
+        for (u32 i = 0; i < sh.nfree; ++i) {
+            DAlloc& old = c.allocs[c.miss_bd[i]];
+            heap_release(c, old.writer_off);
+            heap_release(c, old.rd_off);
+            old.writer_off = old.rd_off = 0;
+        }
+        sh.s.resizes += sh.nfree;
+        sh.s.next_alloc += total_allocs;
+        sh.n_alloc_instr = total;
+        sh.unit_n += total;
+        sh.nfree = 0;
+    }
+    bar();
+}
+
+// ===========================================================================
+// Coherence (Sec. 3.3).  Counting pass: per memory worker, consumers in
+// (chunk, access) order; stale cells grouped by (producer memory, original
+// producer, source allocation); canonical boxes; the memory is marked up to
+// date at once (consumer split).
+// ===========================================================================
+IGN void coherence_count(DevCtx& c, Shared& sh) {
+    const u32 A = sh.t_nacc, K = c.per_dev;
+    for (u32 m = tid(); m < c.n_mem; m += nt()) {
+        if (m < 2) continue;
+        const u32 d = m - 2;
+        u64* key = c.wk_key + (size_t)tid() * c.cap_scr;
+        u32* val = c.wk_val + (size_t)tid() * c.cap_scr;
+        u64* key2 = c.wk_key2 + (size_t)tid() * c.cap_scr;
+        u32* val2 = c.wk_val2 + (size_t)tid() * c.cap_scr;
+        u32 total = 0, kcount = 0;
+        for (u32 k = d * K; k < (d + 1) * K; ++k) {
+            const bool chunk_empty = c.chunk_lo[k] >= c.chunk_hi[k] || sh.t_lo[1] >= sh.t_hi[1] || sh.t_lo[2] >= sh.t_hi[2];
+            if (!chunk_empty) ++kcount;
+            for (u32 j = 0; j < A; ++j) {
+                const u32 idx = k * IG_MAX_ACCESS + j;
+                c.cons_cnt[idx] = 0;
+                c.cons_off[idx] = 0;
+                const Region& r = c.reg[idx];
+                if (chunk_empty || r.empty || !(r.mode & IG_READ)) continue;
+                const u32 b = r.buffer;
+                const DBuf& B = c.bufs[b];
+                const u32* prod = W32(c, B.prod_off);
+                const u32* pmv = W32(c, B.pm_off);
+                u64* mask = W64(c, B.mask_off);
+                u32 n = 0;
+                for (u32 i0 = r.clo[0]; i0 < r.chi[0]; ++i0)
+                    for (u32 i1 = r.clo[1]; i1 < r.chi[1]; ++i1)
+                        for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2) {
+                            const u32 cell = cell_of(B, i0, i1, i2);
+                            const u64* mk = mask + (size_t)cell * c.mw;
+                            if ((mk[m >> 6] >> (m & 63)) & 1) continue;
+                            u64 any = 0;
+                            for (u32 w = 0; w < c.mw; ++w) any |= mk[w];
+                            if (!any) continue;  // never initialised: nothing to copy
+                            const u32 pm = pmv[cell];
+                            const u32 p = eff_w(sh, prod[cell]);
+                            const u32 src = live_containing_cell(c, b, pm, i0, i1, i2);
+                            if (src == 0) set_error(sh, IG_E_DEVICE);
+                            if (n >= c.cap_scr) {
+                                set_error(sh, IG_E_CAPACITY);
+                                break;
+                            }
+                            key[n] = ((u64)pm << 56) | ((u64)p << 24) | (u64)(src & 0xFFFFFF);
+                            val[n] = cell;
+                            ++n;
+                        }
+                if (n == 0) continue;
+                const u32 dst = live_containing(c, b, m, r.lo, r.hi);
+                if (dst == 0) set_error(sh, IG_E_DEVICE);
+                msort_kv(key, val, key2, val2, n);
+                // count, reserve, then write the copies
+                u32 cnt = 0;
+                for (u32 g = 0; g < n;) {
+                    u32 h = g;
+                    while (h < n && key[h] == key[g]) ++h;
+                    cnt += canon_cells(val + g, h - g, B.n[1], B.n[2], [](u32, u32, u32, u32, u32, u32) {});
+                    g = h;
+                }
+                const u32 off = atomicAdd(&sh.copy_top, cnt);
+                if (off + cnt > c.cap_unit) {
+                    set_error(sh, IG_E_CAPACITY);
+                    continue;
+                }
+                u32 o = off;
+                for (u32 g = 0; g < n;) {
+                    u32 h = g;
+                    while (h < n && key[h] == key[g]) ++h;
+                    const u32 pm = (u32)(key[g] >> 56);
+                    const u32 src = (u32)(key[g] & 0xFFFFFF);
+                    const u32 nb = canon_cells(val + g, h - g, B.n[1], B.n[2],
+                                               [&](u32 a0, u32 a1, u32 b0, u32 b1, u32 c0, u32 c1) {
+                                                   CopyRec& cr = c.copies[o++];
+                                                   cr.chunk = k;
+                                                   cr.buffer = b;
+                                                   cr.src_alloc = src;
+                                                   cr.dst_alloc = dst;
+                                                   cr.src_mem = pm;
+                                                   cr.dst_mem = m;
+                                                   cr.clo[0] = a0;
+                                                   cr.chi[0] = a1;
+                                                   cr.clo[1] = b0;
+                                                   cr.chi[1] = b1;
+                                                   cr.clo[2] = c0;
+                                                   cr.chi[2] = c1;
+                                               });
+                    atomicAdd(&c.inbox_cnt[pm], nb);
+                    g = h;
+                }
+                // consumer split: the data is now present on m
+                for (u32 i = 0; i < n; ++i) atomicOr(&mask[(size_t)val[i] * c.mw + (m >> 6)], 1ull << (m & 63));
+                c.cons_off[idx] = off;
+                c.cons_cnt[idx] = cnt;
+                total += cnt;
+            }
+        }
+        c.dev_cnt[d] = total;
+        c.kdev_cnt[d] = kcount;
+    }
+}
+
+// Emission pass: ids, records, edges, updates of the destination maps; the
+// reads of source allocations go to their owners' inboxes.
+IGN void coherence_emit(DevCtx& c, Shared& sh, u32 copy_first) {
+    const u32 A = sh.t_nacc, K = c.per_dev;
+    for (u32 m = tid(); m < c.n_mem; m += nt()) {
+        if (m < 2) continue;
+        const u32 d = m - 2;
+        u32 x = copy_first + c.dev_base[d];
+        for (u32 k = d * K; k < (d + 1) * K; ++k)
+            for (u32 j = 0; j < A; ++j) {
+                const u32 idx = k * IG_MAX_ACCESS + j;
+                for (u32 q = c.cons_off[idx]; q < c.cons_off[idx] + c.cons_cnt[idx]; ++q) {
+                    const CopyRec& cr = c.copies[q];
+                    const DBuf& B = c.bufs[cr.buffer];
+                    const DAlloc& sa = c.allocs[cr.src_alloc];
+                    const DAlloc& da = c.allocs[cr.dst_alloc];
+                    const i64 lo[3] = {bps(c, B, 0)[cr.clo[0]], bps(c, B, 1)[cr.clo[1]], bps(c, B, 2)[cr.clo[2]]};
+                    const i64 hi[3] = {bps(c, B, 0)[cr.chi[0]], bps(c, B, 1)[cr.chi[1]], bps(c, B, 2)[cr.chi[2]]};
+                    const bool inter = cr.src_mem >= 2 && (cr.src_mem - 2) / c.devices != (m - 2) / c.devices;
+                    put_instr(c, x, IG_COPY, inter ? IG_F_INTER_NODE : 0, sh.t_id, k, cr.buffer, m, cr.src_mem,
+                              cr.dst_alloc, cr.src_alloc, lo, hi);
+                    Src s = worker_src(c);
+                    for (u32 i0 = cr.clo[0]; i0 < cr.chi[0]; ++i0)
+                        for (u32 i1 = cr.clo[1]; i1 < cr.chi[1]; ++i1)
+                            for (u32 i2 = cr.clo[2]; i2 < cr.chi[2]; ++i2) {
+                                edges_read(c, sh, s, sa, alloc_local(sa, i0, i1, i2));
+                                edges_write(c, sh, s, da, alloc_local(da, i0, i1, i2));
+                            }
+                    stage(c, sh, x, s);
+                    u32* wr = W32(c, da.writer_off);
+                    u32* rd = W32(c, da.rd_off);
+                    for (u32 i0 = cr.clo[0]; i0 < cr.chi[0]; ++i0)
+                        for (u32 i1 = cr.clo[1]; i1 < cr.chi[1]; ++i1)
+                            for (u32 i2 = cr.clo[2]; i2 < cr.chi[2]; ++i2) {
+                                const u32 l = alloc_local(da, i0, i1, i2);
+                                wr[l] = x;
+                                rd_clear(c, m, &rd[l]);
+                            }
+                    const u32 slot = atomicAdd(&c.inbox_cur[cr.src_mem], 1u);
+                    InboxRec& ib = c.inbox[slot];
+                    ib.alloc = cr.src_alloc;
+                    ib.reader = x;
+                    for (u32 t = 0; t < 3; ++t) {
+                        ib.clo[t] = cr.clo[t];
+                        ib.chi[t] = cr.chi[t];
+                    }
+                    ++x;
+                }
+            }
+    }
+}
+
+IGN void inbox_drain(DevCtx& c, Shared& sh) {
+    for (u32 m = tid(); m < c.n_mem; m += nt()) {
+        const u32 lo = c.inbox_off[m], hi = lo + c.inbox_cnt[m];
+        for (u32 q = lo; q < hi; ++q) {
+            const InboxRec& ib = c.inbox[q];
+            const DAlloc& a = c.allocs[ib.alloc];
+            u32* rd = W32(c, a.rd_off);
+            for (u32 i0 = ib.clo[0]; i0 < ib.chi[0]; ++i0)
+                for (u32 i1 = ib.clo[1]; i1 < ib.chi[1]; ++i1)
+                    for (u32 i2 = ib.clo[2]; i2 < ib.chi[2]; ++i2)
+                        rd_append(c, sh, m, &rd[alloc_local(a, i0, i1, i2)], ib.reader);
+        }
+    }
+}
+
+// ===========================================================================
+// Device kernels, bindings, buffer-map update (Sec. 3.1, 3.2)
+// ===========================================================================
+IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
+    const u32 A = sh.t_nacc, K = c.per_dev;
+    for (u32 m = tid(); m < c.n_mem; m += nt()) {
+        if (m < 2) continue;
+        const u32 d = m - 2;
+        u32 r = 0;
+        for (u32 k = d * K; k < (d + 1) * K; ++k) {
+            const i64 lo[3] = {c.chunk_lo[k], sh.t_lo[1], sh.t_lo[2]};
+            const i64 hi[3] = {c.chunk_hi[k], sh.t_hi[1], sh.t_hi[2]};
+            if (box_empty(lo, hi)) continue;
+            const u32 x = kern_first + c.kdev_base[d] + r;
+            const u64 bi = sh.s.n_binds + (u64)(c.kdev_base[d] + r) * A;
+            ++r;
+            put_instr(c, x, IG_KERNEL, 0, sh.t_id, k, NONE, m, 0xFFFF, 0, 0, lo, hi);
+            u32 al[IG_MAX_ACCESS];
+            for (u32 j = 0; j < A; ++j) {
+                const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
+                al[j] = rg.empty ? 0 : live_containing(c, rg.buffer, m, rg.lo, rg.hi);
+                if (!rg.empty && al[j] == 0) set_error(sh, IG_E_DEVICE);
+                c.b_instr[bi + j] = x;
+                c.b_access[bi + j] = j;
+                c.b_alloc[bi + j] = al[j];
+            }
+            Src s = worker_src(c);
+            for (u32 j = 0; j < A; ++j) {
+                if (!al[j]) continue;
+                const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
+                const DAlloc& a = c.allocs[al[j]];
+                for (u32 i0 = rg.clo[0]; i0 < rg.chi[0]; ++i0)
+                    for (u32 i1 = rg.clo[1]; i1 < rg.chi[1]; ++i1)
+                        for (u32 i2 = rg.clo[2]; i2 < rg.chi[2]; ++i2) {
+                            const u32 l = alloc_local(a, i0, i1, i2);
+                            if (rg.mode & IG_READ) edges_read(c, sh, s, a, l);
+                            if (rg.mode & IG_WRITE) edges_write(c, sh, s, a, l);
+                        }
+            }
+            stage(c, sh, x, s);
+            // reads first, then writes (a cell both read and written ends written)
+            for (u32 j = 0; j < A; ++j) {
+                const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
+                if (!al[j] || !(rg.mode & IG_READ)) continue;
+                const DAlloc& a = c.allocs[al[j]];
+                u32* rd = W32(c, a.rd_off);
+                for (u32 i0 = rg.clo[0]; i0 < rg.chi[0]; ++i0)
+                    for (u32 i1 = rg.clo[1]; i1 < rg.chi[1]; ++i1)
+                        for (u32 i2 = rg.clo[2]; i2 < rg.chi[2]; ++i2)
+                            rd_append(c, sh, m, &rd[alloc_local(a, i0, i1, i2)], x);
+            }
+            for (u32 j = 0; j < A; ++j) {
+                const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
+                if (!al[j] || !(rg.mode & IG_WRITE)) continue;
+                const DAlloc& a = c.allocs[al[j]];
+                const DBuf& B = c.bufs[rg.buffer];
+                u32* wr = W32(c, a.writer_off);
+                u32* rd = W32(c, a.rd_off);
+                u32* prod = W32(c, B.prod_off);
+                u32* pmv = W32(c, B.pm_off);
+                u64* mask = W64(c, B.mask_off);
+                for (u32 i0 = rg.clo[0]; i0 < rg.chi[0]; ++i0)
+                    for (u32 i1 = rg.clo[1]; i1 < rg.chi[1]; ++i1)
+                        for (u32 i2 = rg.clo[2]; i2 < rg.chi[2]; ++i2) {
+                            const u32 l = alloc_local(a, i0, i1, i2);
+                            wr[l] = x;
+                            rd_clear(c, m, &rd[l]);
+                            const u32 cell = cell_of(B, i0, i1, i2);
+                            prod[cell] = x;
+                            pmv[cell] = m;
+                            for (u32 w = 0; w < c.mw; ++w)
+                                mask[(size_t)cell * c.mw + w] = (w == (m >> 6)) ? (1ull << (m & 63)) : 0ull;
+                        }
+            }
+        }
+    }
+}
+
+// ===========================================================================
+// Compile one task: allocation phase, coherence copies, kernels, edges.
+// ===========================================================================
+IGN void load_task(DevCtx& c, Shared& sh, u32 ci) {
+    if (tid() == 0) {
+        const DevCmd& cmd = c.cmds[ci];
+        sh.t_cmd = ci;
+        sh.t_id = cmd.arg;
+        sh.t_dims = cmd.task.dims;
+        sh.t_nacc = cmd.task.n_access;
+        for (u32 d = 0; d < 3; ++d) {
+            sh.t_lo[d] = cmd.task.box.min[d];
+            sh.t_hi[d] = cmd.task.box.max[d];
+        }
+    }
+    bar();
+}
+
+IGN void compile_task(DevCtx& c, Shared& sh, u32 ci) {
+    load_task(c, sh, ci);
+    compute_regions(c, sh);
+    unit_begin(c, sh);
+    alloc_phase(c, sh);
+    if (failed(sh)) return;
+    for (u32 i = tid(); i < c.n_mem; i += nt()) c.inbox_cnt[i] = 0;
+    bar();
+    coherence_count(c, sh);
+    if (failed(sh)) return;
+    // scans: copies and kernels per device, inbox slots per memory
+    for (u32 i = tid(); i < c.n_dev; i += nt()) {
+        c.dev_base[i] = c.dev_cnt[i];
+        c.kdev_base[i] = c.kdev_cnt[i];
+    }
+    for (u32 i = tid(); i < c.n_mem; i += nt()) c.inbox_off[i] = c.inbox_cnt[i];
+    bar();
+    const u32 n_copies = block_exscan(sh, c.dev_base, c.n_dev);
+    const u32 n_kernels = block_exscan(sh, c.kdev_base, c.n_dev);
+    block_exscan(sh, c.inbox_off, c.n_mem);
+    for (u32 i = tid(); i < c.n_mem; i += nt()) c.inbox_cur[i] = c.inbox_off[i];
+    const u32 n_task = sh.unit_n + n_copies + n_kernels;
+    if (tid() == 0) {
+        if ((u64)sh.unit_first + n_task > c.cap_instr || n_task > c.cap_unit ||
+            sh.s.n_binds + (u64)n_kernels * sh.t_nacc > c.cap_binds)
+            set_error(sh, IG_E_CAPACITY);
+    }
+    if (failed(sh)) return;
+    const u32 copy_first = sh.unit_first + sh.unit_n;
+    const u32 kern_first = copy_first + n_copies;
+    coherence_emit(c, sh, copy_first);
+    bar();
+    inbox_drain(c, sh);
+    bar();
+    kernels_emit(c, sh, kern_first);
+    bar();
+    if (tid() == 0) sh.unit_n += n_copies + n_kernels;
+    bar();
+    unit_end(c, sh);
+    if (tid() == 0) sh.s.n_binds += (u64)n_kernels * sh.t_nacc;
+    bar();
+}
+
+// ===========================================================================
+// Lookahead (Sec. 4.3): command queue, allocating predicate, plans.
+// ===========================================================================
+IGD bool covered(DevCtx& c, Shared& sh, u32 b, u32 m, const i64 lo[3], const i64 hi[3]) {
+    const u32 pi = b * c.n_mem + m;
+    if (sh.s.qlen > 0 && c.plan_n[pi] != NONE) {
+        const i64* p = c.plan + (size_t)pi * MAX_PLAN * 6;
+        for (u32 i = 0; i < c.plan_n[pi]; ++i)
+            if (box_contains(p + 6 * i, p + 6 * i + 3, lo, hi)) return true;
+        return false;
+    }
+    return live_containing(c, b, m, lo, hi) != 0;
+}
+
+// allocating? (regions of the current task are in c.reg)
+IGN bool task_allocating(DevCtx& c, Shared& sh) {
+    const u32 A = sh.t_nacc, C = c.chunks;
+    if (tid() == 0) sh.flag = 0;
+    bar();
+    for (u32 idx = tid(); idx < C * A; idx += nt()) {
+        const u32 k = idx / A, j = idx % A;
+        const Region& r = c.reg[k * IG_MAX_ACCESS + j];
+        if (r.empty) continue;
+        if (!covered(c, sh, r.buffer, mem_of_chunk(c, k), r.lo, r.hi)) sh.flag = 1;
+    }
+    bar();
+    return sh.flag != 0;
+}
+
+IGN void plan_merge(DevCtx& c, Shared& sh) {
+    const u32 A = sh.t_nacc, K = c.per_dev;
+    for (u32 m = tid(); m < c.n_mem; m += nt()) {
+        if (m < 2) continue;
+        const u32 d = m - 2;
+        i64* bx = c.wk_box + (size_t)tid() * c.cap_box * 6;
+        for (u32 b = 0; b < sh.s.n_buffers; ++b) {
+            bool any = false;
+            for (u32 k = d * K; k < (d + 1) * K && !any; ++k)
+                for (u32 j = 0; j < A; ++j) {
+                    const Region& r = c.reg[k * IG_MAX_ACCESS + j];
+                    if (!r.empty && r.buffer == b) any = true;
+                }
+            if (!any) continue;
+            const u32 pi = b * c.n_mem + m;
+            u32 n = 0;
+            if (c.plan_n[pi] != NONE) {
+                const i64* p = c.plan + (size_t)pi * MAX_PLAN * 6;
+                for (u32 i = 0; i < c.plan_n[pi] * 6; ++i) bx[i] = p[i];
+                n = c.plan_n[pi];
+            } else {
+                const u32 lb = pi * MAX_LIVE;
+                for (u32 i = 0; i < c.live_n[pi]; ++i) {
+                    const DAlloc& a = c.allocs[c.live[lb + i]];
+                    for (u32 t = 0; t < 3; ++t) {
+                        bx[6 * n + t] = a.lo[t];
+                        bx[6 * n + 3 + t] = a.hi[t];
+                    }
+                    ++n;
+                }
+            }
+            for (u32 k = d * K; k < (d + 1) * K; ++k)
+                for (u32 j = 0; j < A; ++j) {
+                    const Region& r = c.reg[k * IG_MAX_ACCESS + j];
+                    if (r.empty || r.buffer != b) continue;
+                    if (n >= c.cap_box) {
+                        set_error(sh, IG_E_CAPACITY);
+                        break;
+                    }
+                    for (u32 t = 0; t < 3; ++t) {
+                        bx[6 * n + t] = r.lo[t];
+                        bx[6 * n + 3 + t] = r.hi[t];
+                    }
+                    ++n;
+                }
+            n = merge_fixpoint(bx, n);
+            if (n > MAX_PLAN) {
+                set_error(sh, IG_E_CAPACITY);
+                continue;
+            }
+            i64* p = c.plan + (size_t)pi * MAX_PLAN * 6;
+            for (u32 i = 0; i < n * 6; ++i) p[i] = bx[i];
+            c.plan_n[pi] = n;
+        }
+    }
+    bar();
+}
+
+IGN void compile_entry(DevCtx& c, Shared& sh, u32 entry) {
+    if (entry & 0x80000000u) {
+        compile_sync(c, sh, false);
+    } else {
+        compile_task(c, sh, entry);
+    }
+}
+
+IGN void flush_queue(DevCtx& c, Shared& sh) {
+    const u32 n = uniform(sh.s.qlen);
+    for (u32 i = 0; i < n && !failed(sh); ++i) {
+        if (tid() == 0) {
+            sh.win_first = i + 1;
+            sh.win_n = n - i - 1;
+        }
+        bar();
+        compile_entry(c, sh, c.queue[i]);
+        bar();
+    }
+    const u32 NP = sh.s.n_buffers * c.n_mem;
+    for (u32 i = tid(); i < NP; i += nt()) c.plan_n[i] = NONE;
+    if (tid() == 0) {
+        sh.s.qlen = 0;
+        sh.s.h = 0;
+        sh.win_n = 0;
+    }
+    bar();
+}
+
+IGN void push_command(DevCtx& c, Shared& sh, u32 entry, bool allocating) {
+    const u32 qlen = uniform(sh.s.qlen);
+    if (!c.lookahead || (qlen == 0 && !allocating)) {
+        if (tid() == 0) sh.win_n = 0;
+        bar();
+        compile_entry(c, sh, entry);
+        return;
+    }
+    if (allocating) plan_merge(c, sh);
+    if (tid() == 0) {
+        if (sh.s.qlen >= c.cap_queue) {
+            set_error(sh, IG_E_CAPACITY);
+        } else {
+            c.queue[sh.s.qlen++] = entry;
+            if (allocating)
+                sh.s.h = 0;
+            else if (entry & 0x80000000u)
+                sh.s.h += 1;
+        }
+    }
+    if (failed(sh)) return;
+    const bool full = sh.s.h >= c.flush_horizons || (c.queue_cap != 0 && sh.s.qlen >= c.queue_cap);
+    bar();
+    if (full) flush_queue(c, sh);
+}
+
+// ===========================================================================
+// Command intake
+// ===========================================================================
+IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
+    load_task(c, sh, ci);
+    if (tid() == 0) *c.miss_n = 0;
+    bar();
+    compute_regions(c, sh);
+    if (uniform(*c.miss_n)) {
+        refine_all(c, sh);
+        if (failed(sh)) return;
+        compute_regions(c, sh);
+        if (uniform(*c.miss_n) && tid() == 0) set_error(sh, IG_E_DEVICE);
+        if (failed(sh)) return;
+    }
+    // Sec. 4.4 checks
+    const u32 A = sh.t_nacc, C = c.chunks, t = sh.t_id;
+    if (tid() == 0) {
+        sh.flag = 0;
+        sh.flag2 = 0;
+    }
+    bar();
+    for (u32 idx = tid(); idx < C * A; idx += nt()) {
+        const u32 k = idx / A, j = idx % A;
+        const Region& r = c.reg[k * IG_MAX_ACCESS + j];
+        if (r.empty) continue;
+        const DBuf& B = c.bufs[r.buffer];
+        u64* stamp = W64(c, B.stamp_off);
+        const u32* init = W32(c, B.init_off);
+        const u64 mine = ((u64)(t + 1) << 32) | k;
+        for (u32 i0 = r.clo[0]; i0 < r.chi[0]; ++i0)
+            for (u32 i1 = r.clo[1]; i1 < r.chi[1]; ++i1)
+                for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2) {
+                    const u32 cell = cell_of(B, i0, i1, i2);
+                    if ((r.mode & IG_READ) && !init[cell]) sh.flag2 = 1;
+                    if (r.mode & IG_WRITE) {
+                        u64 old = stamp[cell];
+                        while (true) {
+                            if ((old >> 32) == (u64)(t + 1)) {
+                                if (old != mine) sh.flag = 1;
+                                break;
+                            }
+                            const u64 seen = atomicCAS((unsigned long long*)&stamp[cell], (unsigned long long)old,
+                                                       (unsigned long long)mine);
+                            if (seen == old) break;
+                            old = seen;
+                        }
+                    }
+                }
+    }
+    const bool overlap = uniform(sh.flag) != 0;
+    if (tid() == 0) {
+        const i32 st = overlap ? IG_E_OVERLAPPING_WRITE : (sh.flag2 ? IG_W_UNINIT_READ : IG_OK);
+        c.task_status[sh.s.n_tasks] = st;
+        sh.s.n_tasks += 1;
+        if (overlap) sh.s.rejected += 1;
+        if (st == IG_W_UNINIT_READ) sh.s.warnings += 1;
+    }
+    bar();
+    if (overlap) return;
+    for (u32 idx = tid(); idx < C * A; idx += nt()) {
+        const u32 k = idx / A, j = idx % A;
+        const Region& r = c.reg[k * IG_MAX_ACCESS + j];
+        if (r.empty || !(r.mode & IG_WRITE)) continue;
+        const DBuf& B = c.bufs[r.buffer];
+        u32* init = W32(c, B.init_off);
+        for (u32 i0 = r.clo[0]; i0 < r.chi[0]; ++i0)
+            for (u32 i1 = r.clo[1]; i1 < r.chi[1]; ++i1)
+                for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2) init[cell_of(B, i0, i1, i2)] = 1;
+    }
+    bar();
+    const bool allocating = c.lookahead ? task_allocating(c, sh) : false;
+    push_command(c, sh, ci, allocating);
+    if (failed(sh)) return;
+    if (tid() == 0) {
+        sh.s.tasks_since_sync += 1;
+        sh.do_horizon = 0;
+        if (sh.s.tasks_since_sync == c.horizon_step) {
+            sh.s.tasks_since_sync = 0;
+            sh.do_horizon = 1;
+        }
+    }
+    if (uniform(sh.do_horizon)) push_command(c, sh, 0x80000000u, false);
+}
+
+IGN void create_buffer(DevCtx& c, Shared& sh, const DevCmd& cmd) {
+    if (tid() == 0) {
+        const u32 b = sh.s.n_buffers;
+        if (b >= MAX_BUF) {
+            set_error(sh, IG_E_CAPACITY);
+        } else {
+            DBuf& B = c.bufs[b];
+            B.alive = 1;
+            B.dims = cmd.dims;
+            B.init = cmd.init;
+            B.user_alloc = 0;
+            for (u32 d = 0; d < 3; ++d) {
+                B.ext[d] = cmd.ext[d];
+                B.n[d] = 1;
+                B.bp_off[d] = heap_alloc(c, sh, 4);
+                if (B.bp_off[d]) {
+                    WI64(c, B.bp_off[d])[0] = 0;
+                    WI64(c, B.bp_off[d])[1] = cmd.ext[d];
+                }
+            }
+            B.ncells = 1;
+            B.prod_off = heap_alloc(c, sh, 1);
+            B.pm_off = heap_alloc(c, sh, 1);
+            B.mask_off = heap_alloc(c, sh, 2 * c.mw);
+            B.init_off = heap_alloc(c, sh, 1);
+            B.stamp_off = heap_alloc(c, sh, 2);
+            if (!sh.s.error) {
+                W32(c, B.prod_off)[0] = cmd.init ? sh.s.S : NONE;
+                W32(c, B.pm_off)[0] = cmd.init ? 0 : NONE;
+                for (u32 w = 0; w < c.mw; ++w) W64(c, B.mask_off)[w] = (cmd.init && w == 0) ? 1ull : 0ull;
+                W32(c, B.init_off)[0] = cmd.init ? 1 : 0;
+                W64(c, B.stamp_off)[0] = 0;
+                for (u32 m = 0; m < c.n_mem; ++m) {
+                    c.live_n[b * c.n_mem + m] = 0;
+                    c.plan_n[b * c.n_mem + m] = NONE;
+                }
+                if (cmd.init) {
+                    // host data lives in user memory M0, produced before the current sync point
+                    const u32 id = sh.s.next_alloc++;
+                    if (id >= c.cap_allocs) {
+                        set_error(sh, IG_E_CAPACITY);
+                    } else {
+                        DAlloc& a = c.allocs[id];
+                        a.buffer = b;
+                        a.mem = 0;
+                        a.alive = 1;
+                        a.ncells = 1;
+                        for (u32 d = 0; d < 3; ++d) {
+                            a.lo[d] = 0;
+                            a.hi[d] = cmd.ext[d];
+                            a.clo[d] = 0;
+                            a.chi[d] = 1;
+                        }
+                        a.writer_off = heap_alloc(c, sh, 1);
+                        a.rd_off = heap_alloc(c, sh, 1);
+                        if (!sh.s.error) {
+                            W32(c, a.writer_off)[0] = sh.s.S;
+                            W32(c, a.rd_off)[0] = 0;
+                        }
+                        c.live[(b * c.n_mem + 0) * MAX_LIVE] = id;
+                        c.live_n[b * c.n_mem + 0] = 1;
+                        B.user_alloc = id;
+                    }
+                }
+                sh.s.n_buffers = b + 1;
+            }
+        }
+    }
+    bar();
+}
+
+// Sec. 3.2: a destroyed buffer's device allocations are freed (ascending id)
+IGN void destroy_buffer(DevCtx& c, Shared& sh, u32 b) {
+    unit_begin(c, sh);
+    if (tid() == 0) {
+        u32 n = 0;
+        for (u32 m = 2; m < c.n_mem; ++m) {
+            const u32 lb = (b * c.n_mem + m) * MAX_LIVE;
+            for (u32 i = 0; i < c.live_n[b * c.n_mem + m]; ++i) c.cons_off[n++] = c.live[lb + i];
+        }
+        for (u32 i = 1; i < n; ++i)
+            for (u32 j = i; j > 0 && c.cons_off[j] < c.cons_off[j - 1]; --j) {
+                const u32 v = c.cons_off[j];
+                c.cons_off[j] = c.cons_off[j - 1];
+                c.cons_off[j - 1] = v;
+            }
+        if ((u64)sh.unit_first + n > c.cap_instr || n > c.cap_unit) set_error(sh, IG_E_CAPACITY);
+        sh.unit_n = n;
+    }
+    if (failed(sh)) return;
+    const u32 n = sh.unit_n;
+    for (u32 i = 0; i < n; ++i) {
+        DAlloc& a = c.allocs[c.cons_off[i]];
+        if (owner_of(a.mem) != tid()) continue;
+        const u32 x = sh.unit_first + i;
+        put_instr(c, x, IG_FREE, 0, NONE, NONE, b, a.mem, 0xFFFF, c.cons_off[i], 0, a.lo, a.hi);
+        Src s = worker_src(c);
+        free_edges(c, sh, s, a);
+        stage(c, sh, x, s);
+        release_readers(c, a);
+    }
+    bar();
+    unit_end(c, sh);
+    if (tid() == 0) {
+        DBuf& B = c.bufs[b];
+        for (u32 i = 0; i < n; ++i) {
+            DAlloc& a = c.allocs[c.cons_off[i]];
+            a.alive = 0;
+            heap_release(c, a.writer_off);
+            heap_release(c, a.rd_off);
+        }
+        for (u32 m = 0; m < c.n_mem; ++m) c.live_n[b * c.n_mem + m] = 0;
+        B.alive = 0;
+    }
+    bar();
+    // the user allocation's reader lists go back to M0's free list
+    if (c.bufs[b].user_alloc && owner_of(0) == tid()) release_readers(c, c.allocs[c.bufs[b].user_alloc]);
+    bar();
+    if (tid() == 0) {
+        DBuf& B = c.bufs[b];
+        if (B.user_alloc) {
+            DAlloc& ua = c.allocs[B.user_alloc];
+            ua.alive = 0;
+            heap_release(c, ua.writer_off);
+            heap_release(c, ua.rd_off);
+        }
+        for (u32 d = 0; d < 3; ++d) heap_release(c, B.bp_off[d]);
+        heap_release(c, B.prod_off);
+        heap_release(c, B.pm_off);
+        heap_release(c, B.mask_off);
+        heap_release(c, B.init_off);
+        heap_release(c, B.stamp_off);
+    }
+    bar();
+}
+
+IGN void init_state(DevCtx& c, Shared& sh) {
+    // I0, the initial epoch, and empty tables
+    for (u32 i = tid(); i < 32; i += nt()) c.heap_free[i] = 0;
+    for (u32 i = tid(); i < c.n_mem; i += nt()) c.rb_free[i] = 0;
+    if (tid() == 0) {
+        Scalars& s = sh.s;
+        s.n_instr = 1;
+        s.n_edges = 0;
+        s.n_binds = 0;
+        s.warnings = s.rejected = s.resizes = 0;
+        s.cmd_next = 0;
+        s.n_tasks = 0;
+        s.next_alloc = 1;
+        s.S = 0;
+        s.E = 0;
+        s.pending = NONE;
+        s.last_sync = 0;
+        s.tasks_since_sync = 0;
+        s.h = 0;
+        s.qlen = 0;
+        s.n_buffers = 0;
+        s.finished = 0;
+        s.heap_top = 16;
+        s.rb_top = 1;
+        s.error = 0;
+        const i64 z[3] = {0, 0, 0};
+        put_instr(c, 0, IG_EPOCH, 0, NONE, NONE, NONE, 0xFFFF, 0xFFFF, 0, 0, z, z);
+    }
+    bar();
+}
+
+IGN void analyse(DevCtx& c, Shared& sh) {
+    if (tid() == 0) sh.s = c.s;
+    bar();
+    if (uniform(sh.s.cmd_next == 0 && sh.s.n_instr == 0)) init_state(c, sh);
+    while (true) {
+        const u32 ci = sh.s.cmd_next;
+        const bool go = ci < c.cmd_end && sh.s.error == 0;
+        bar();
+        if (!go) break;
+        const DevCmd& cmd = c.cmds[ci];
+        switch (cmd.kind) {
+            case CMD_BUFFER:
+                create_buffer(c, sh, cmd);
+                break;
+            case CMD_TASK:
+                intake_task(c, sh, ci);
+                break;
+            case CMD_EPOCH:
+                flush_queue(c, sh);
+                if (tid() == 0) sh.s.tasks_since_sync = 0;
+                bar();
+                compile_sync(c, sh, true);
+                break;
+            case CMD_DESTROY:
+                flush_queue(c, sh);
+                destroy_buffer(c, sh, cmd.arg);
+                break;
+            case CMD_SHUTDOWN: {
+                flush_queue(c, sh);
+                const u32 nb = uniform(sh.s.n_buffers);
+                for (u32 b = 0; b < nb && !failed(sh); ++b)
+                    if (uniform(c.bufs[b].alive)) destroy_buffer(c, sh, b);
+                if (tid() == 0) sh.s.tasks_since_sync = 0;
+                bar();
+                compile_sync(c, sh, true);
+                if (tid() == 0) sh.s.finished = 1;
+                break;
+            }
+            default:
+                if (tid() == 0) set_error(sh, IG_E_INVALID);
+        }
+        bar();
+        if (tid() == 0 && !sh.s.error) sh.s.cmd_next = ci + 1;
+        bar();
+    }
+    bar();
+    if (tid() == 0) c.s = sh.s;
+}
+
+// ===========================================================================
+// Record digests and statistics (parallel over records)
+// ===========================================================================
+IGD u64 splitmix64(u64 x) {
+    u64 z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+IGD u64 fnv_words(const u64* w, u32 n) {
+    u64 h = 0xcbf29ce484222325ull;
+    for (u32 i = 0; i < n; ++i)
+        for (u32 b = 0; b < 8; ++b) {
+            h ^= (w[i] >> (8 * b)) & 0xFF;
+            h *= 0x100000001b3ull;
+        }
+    return h;
+}
+
+IGD u64 w32(u32 v) { return v; }
+IGD u64 w16(u16 v) { return v; }
+
+IGD void instr_words(const DevCtx& c, u64 i, u64 w[12]) {
+    w[0] = i;
+    w[1] = (u64)c.i_kind[i] | ((u64)c.i_flags[i] << 8) | ((u64)c.i_mem[i] << 16) | ((u64)c.i_src_mem[i] << 32);
+    w[2] = (u64)c.i_task[i] | ((u64)c.i_chunk[i] << 32);
+    w[3] = c.i_buffer[i];
+    w[4] = c.i_alloc[i];
+    w[5] = c.i_src_alloc[i];
+    for (u32 d = 0; d < 6; ++d) w[6 + d] = (u64)c.i_box[d * c.cap_instr + i];
+}
+
+}  // namespace igd
+
+using namespace igd;
+
+// ===========================================================================
+// Kernels
+// ===========================================================================
+#ifndef IG_HOST_SIM
+__global__ void __launch_bounds__(1024) ig_analyse(DevCtx* const* ctxs) {
+    __shared__ Shared sh;
+    analyse(*ctxs[blockIdx.x], sh);
+}
+
+__global__ void ig_pack_instructions(const DevCtx* c, u64 first, u64 n, ig_instruction* out) {
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const u64 x = first + i;
+    ig_instruction r;
+    r.id = x;
+    r.kind = c->i_kind[x];
+    r.flags = c->i_flags[x];
+    r.mem = c->i_mem[x];
+    r.src_mem = c->i_src_mem[x];
+    r.pad0 = 0;
+    r.task = c->i_task[x];
+    r.chunk = c->i_chunk[x];
+    r.buffer = c->i_buffer[x];
+    r.pad1 = 0;
+    r.alloc = c->i_alloc[x];
+    r.src_alloc = c->i_src_alloc[x];
+    for (u32 d = 0; d < 3; ++d) {
+        r.box.min[d] = c->i_box[d * c->cap_instr + x];
+        r.box.max[d] = c->i_box[(3 + d) * c->cap_instr + x];
+    }
+    out[i] = r;
+}
+
+__global__ void ig_pack_bindings(const DevCtx* c, u64 first, u64 n, ig_binding* out) {
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ig_binding r;
+    r.instr = c->b_instr[first + i];
+    r.access = c->b_access[first + i];
+    r.pad = 0;
+    r.alloc = c->b_alloc[first + i];
+    out[i] = r;
+}
+
+__global__ void ig_pack_edges(const DevCtx* c, u64 first, u64 n, ig_edge* out) {
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ig_edge r;
+    r.from = c->e_from[first + i];
+    r.to = c->e_to[first + i];
+    r.kinds = c->e_kinds[first + i];
+    r.pad = 0;
+    out[i] = r;
+}
+
+__global__ void __launch_bounds__(256) ig_stats_kernel(const DevCtx* c, u64 ni, u64 nb, u64 ne, DevStats* out) {
+    __shared__ unsigned long long acc[3 + 8 + 5];
+    if (threadIdx.x < 16) acc[threadIdx.x] = 0;
+    __syncthreads();
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    unsigned long long dig[3] = {0, 0, 0};
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < ni; i += stride) {
+        u64 w[12];
+        instr_words(*c, i, w);
+        dig[0] += splitmix64(fnv_words(w, 12) ^ splitmix64(i));
+        atomicAdd(&acc[3 + (c->i_kind[i] & 7)], 1ull);
+    }
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += stride) {
+        u64 w[3] = {c->b_instr[i], c->b_access[i], c->b_alloc[i]};
+        dig[1] += splitmix64(fnv_words(w, 3) ^ splitmix64(i));
+    }
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += stride) {
+        u64 w[3] = {c->e_from[i], c->e_to[i], c->e_kinds[i]};
+        dig[2] += splitmix64(fnv_words(w, 3) ^ splitmix64(i));
+        const u32 k = c->e_kinds[i];
+        for (u32 b = 0; b < 5; ++b)
+            if (k & (1u << b)) atomicAdd(&acc[11 + b], 1ull);
+    }
+    for (u32 q = 0; q < 3; ++q) atomicAdd(&acc[q], dig[q]);
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        unsigned long long* dst = threadIdx.x < 3 ? &out->digest[threadIdx.x]
+                                  : threadIdx.x < 11 ? &out->per_kind[threadIdx.x - 3]
+                                                     : &out->per_dep[threadIdx.x - 11];
+        atomicAdd(dst, acc[threadIdx.x]);
+    }
+}
+
+namespace igrt {
+static thread_local char g_err[256];
+static int check(hipError_t e) {
+    if (e != hipSuccess) {
+        snprintf(g_err, sizeof g_err, "%s", hipGetErrorString(e));
+        return -1;
+    }
+    return 0;
+}
+const char* last_error() { return g_err; }
+int dev_malloc(void** p, size_t bytes) { return check(hipMalloc(p, bytes)); }
+int dev_free(void* p) { return check(hipFree(p)); }
+int host_malloc_pinned(void** p, size_t bytes) { return check(hipHostMalloc(p, bytes, hipHostMallocDefault)); }
+int host_free_pinned(void* p) { return check(hipHostFree(p)); }
+int copy_h2d(void* dst, const void* src, size_t bytes, void* stream) {
+    return check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, (hipStream_t)stream));
+}
+int copy_d2h(void* dst, const void* src, size_t bytes, void* stream) {
+    return check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, (hipStream_t)stream));
+}
+int memset_d(void* dst, int v, size_t bytes, void* stream) {
+    return check(hipMemsetAsync(dst, v, bytes, (hipStream_t)stream));
+}
+int stream_sync(void* stream) { return check(hipStreamSynchronize((hipStream_t)stream)); }
+int launch_analyse(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, void* stream) {
+    hipLaunchKernelGGL(ig_analyse, dim3(n_blocks), dim3(threads), 0, (hipStream_t)stream, ptrs);
+    return check(hipGetLastError());
+}
+static unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+int launch_pack_instructions(const DevCtx* c, uint64_t first, uint64_t n, ig_instruction* out, void* stream) {
+    if (!n) return 0;
+    hipLaunchKernelGGL(ig_pack_instructions, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, c, first, n, out);
+    return check(hipGetLastError());
+}
+int launch_pack_bindings(const DevCtx* c, uint64_t first, uint64_t n, ig_binding* out, void* stream) {
+    if (!n) return 0;
+    hipLaunchKernelGGL(ig_pack_bindings, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, c, first, n, out);
+    return check(hipGetLastError());
+}
+int launch_pack_edges(const DevCtx* c, uint64_t first, uint64_t n, ig_edge* out, void* stream) {
+    if (!n) return 0;
+    hipLaunchKernelGGL(ig_pack_edges, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, c, first, n, out);
+    return check(hipGetLastError());
+}
+int launch_stats(const DevCtx* c, uint64_t ni, uint64_t nb, uint64_t ne, DevStats* out, void* stream) {
+    uint64_t m = ni > ne ? ni : ne;
+    unsigned blocks = blocks_for(m > 0 ? m : 1, 256);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(ig_stats_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, c, ni, nb, ne, out);
+    return check(hipGetLastError());
+}
+}  // namespace igrt
+#endif

@@ -1,0 +1,45 @@
+"""Helpers comparing HIP-path output with the oracle, record by record."""
+import numpy as np
+
+
+def first_difference(a: np.ndarray, b: np.ndarray):
+    n = min(len(a), len(b))
+    if n:
+        ra = a[:n].view(np.uint8).reshape(n, -1)
+        rb = b[:n].view(np.uint8).reshape(n, -1)
+        bad = np.nonzero((ra != rb).any(axis=1))[0]
+        if len(bad):
+            return int(bad[0])
+    if len(a) != len(b):
+        return n
+    return None
+
+
+def assert_same(want, got, name=""):
+    """Bit-exact equality of instructions, bindings, edges and task statuses
+    (integer output: no tolerance)."""
+    for key in ("instructions", "bindings", "edges", "status"):
+        a, b = want[key], got[key]
+        i = first_difference(a, b)
+        assert i is None, (f"{name}: {key} differ at record {i} (len {len(a)} vs {len(b)}):\n"
+                           f"  oracle {a[i] if i < len(a) else None}\n  hip    {b[i] if i < len(b) else None}")
+
+
+def record_words(out):
+    """The digest words of each record list (see the digest definition)."""
+    ins = out["instructions"]
+    w = np.zeros((len(ins), 12), dtype=np.uint64)
+    w[:, 0] = ins["id"]
+    w[:, 1] = (ins["kind"].astype(np.uint64) | (ins["flags"].astype(np.uint64) << np.uint64(8))
+               | (ins["mem"].astype(np.uint64) << np.uint64(16)) | (ins["src_mem"].astype(np.uint64) << np.uint64(32)))
+    w[:, 2] = ins["task"].astype(np.uint64) | (ins["chunk"].astype(np.uint64) << np.uint64(32))
+    w[:, 3] = ins["buffer"]
+    w[:, 4] = ins["alloc"]
+    w[:, 5] = ins["src_alloc"]
+    w[:, 6:9] = ins["min"].astype(np.uint64)
+    w[:, 9:12] = ins["max"].astype(np.uint64)
+    b = out["bindings"]
+    wb = np.stack([b["instr"], b["access"].astype(np.uint64), b["alloc"]], axis=1).astype(np.uint64)
+    e = out["edges"]
+    we = np.stack([e["from"], e["to"], e["kinds"].astype(np.uint64)], axis=1).astype(np.uint64)
+    return w, wb, we

@@ -1,0 +1,128 @@
+"""Parity of the HIP path (libig, gfx950) with the CPU oracle.
+
+Integer output: instructions, bindings, edges and per-task statuses must be
+identical record by record, in canonical order.  Every call goes through the
+C ABI of include/ig.h via the ctypes binding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from parity import assert_same, record_words
+from paper_2503_10516_amd import binding as B
+from paper_2503_10516_amd import streams as S
+
+pytestmark = pytest.mark.gpu
+
+SCENARIOS = [
+    ("nbody_example", S.nbody_example),
+    ("stencil1d", lambda: S.stencil_1d()),
+    ("stencil1d_nola", lambda: S.stencil_1d(lookahead=0)),
+    ("resize0", lambda: S.resize_example(0)),
+    ("resize1", lambda: S.resize_example(1)),
+    ("growing", lambda: S.growing(width=840, steps=32)),
+    ("growing_nola", lambda: S.growing(width=840, steps=32, lookahead=0)),
+    ("growing_cap4", lambda: S.growing(width=840, steps=32, queue_cap=4)),
+    ("stencil2d_small", lambda: S.stencil_2d(side=256, tasks=24, nodes=2, devices=4, chunks=16)),
+    ("nbody_small", lambda: S.nbody(n=4096, steps=6, nodes=4, devices=4, chunks=32)),
+]
+
+
+def run_both(s, **kw):
+    print(f"[gpu] {s.name} tasks={s.n_tasks} chunks={s.chunks} {kw}", flush=True)
+    return oracle.run_stream(s), B.run_stream(s, **kw)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+@pytest.mark.parametrize("name,make", SCENARIOS, ids=[s[0] for s in SCENARIOS])
+def test_scenarios(name, make):
+    want, got = run_both(make())
+    assert_same(want, got, name)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_streams(seed):
+    s = S.random_small(seed)
+    want, got = run_both(s)
+    assert_same(want, got, s.name)
+
+
+@pytest.mark.parametrize("threads", [64, 128, 1024])
+def test_workgroup_size_does_not_change_output(threads):
+    s = S.stencil_2d(side=512, tasks=20, nodes=4, devices=8, chunks=64)
+    want, got = run_both(s, threads=threads)
+    assert_same(want, got, f"{s.name}@{threads}")
+
+
+def test_device_digest_matches_records():
+    s = S.nbody(n=1 << 12, steps=4, nodes=2, devices=4, chunks=16)
+    want, got = run_both(s)
+    assert_same(want, got, s.name)
+    w, wb, we = record_words(got)
+    st = got["stats"]
+    assert st["digest_instructions"] == oracle.digest_words(w) == want["stats"]["digest_instructions"]
+    assert st["digest_bindings"] == oracle.digest_words(wb) == want["stats"]["digest_bindings"]
+    assert st["digest_edges"] == oracle.digest_words(we) == want["stats"]["digest_edges"]
+    assert st["per_kind"] == want["stats"]["per_kind"] and st["per_dep"] == want["stats"]["per_dep"]
+
+
+def test_stencil2d_full_size():
+    """The 2-D stencil at its full size: 4096^2, 1000 tasks, 16x8 devices, 128
+    chunks -- every record compared."""
+    want, got = run_both(S.stencil_2d())
+    assert len(got["instructions"]) == 382638
+    assert_same(want, got, "stencil2d")
+
+
+def test_nbody_full_chunks_reduced_steps():
+    want, got = run_both(S.nbody(steps=20))
+    assert_same(want, got, "nbody20")
+
+
+def test_rewind_reanalyses_identically():
+    s = S.stencil_1d(n=1024, tasks=32)
+    ctx = B.make_context(s)
+    ctx.record(s)
+    ctx.flush()
+    assert ctx.sync() == 0
+    first = ctx.fetch_all()
+    ctx.rewind()
+    ctx.flush()
+    assert ctx.sync() == 0
+    second = ctx.fetch_all()
+    ctx.close()
+    for k in first:
+        assert first[k].tobytes() == second[k].tobytes()
+
+
+def test_incremental_windows_match_one_window():
+    """Flushing after every command gives the same graph as one flush."""
+    s = S.growing(width=840, steps=24, queue_cap=5)
+    want = oracle.run_stream(s)
+    ctx = B.make_context(s)
+    for c in s.cmds:
+        ctx.record(S.Stream(s.nodes, s.devices, s.chunks, cmds=[c]))
+        ctx.flush()
+    assert ctx.sync() == 0
+    got = ctx.fetch_all()
+    ctx.close()
+    assert_same(want, got, "incremental")
+
+
+def test_overlapping_write_status():
+    s = S.Stream(1, 2, 2, lookahead=0)
+    b = s.buffer(1, (64,), 4, S.INIT_HOST)
+    s.task(1, (0,), (64,), [S.Access(b, S.WRITE, S.ONE_TO_ONE)])
+    s.task(1, (0,), (64,), [S.Access(b, S.WRITE, S.ALL)])
+    s.task(1, (0,), (64,), [S.Access(b, S.READ, S.ALL)])
+    s.shutdown()
+    want, got = run_both(s)
+    assert list(got["status"]) == [0, -2, 0]
+    assert_same(want, got, "overlap")
