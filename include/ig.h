@@ -135,10 +135,10 @@ typedef struct ig_context_desc {
     uint32_t queue_cap;         /* flush when the queue holds this many commands (0: unbounded) */
     uint32_t threads;           /* workgroup size of this stream's analysis (0: 256); tuning only */
     uint64_t cap_commands;      /* recorded commands (0: 65536) */
-    uint64_t cap_instructions;  /* output instructions (0: 1<<22) */
+    uint64_t cap_instructions;  /* output instructions (0: 1<<20) */
     uint64_t cap_edges;         /* output edges (0: 4 * cap_instructions) */
     uint64_t cap_state_words;   /* 32-bit words for region maps and grids (0: 1<<24) */
-    uint64_t cap_unit;          /* instructions/edges staged per compiled command (0: 1<<20) */
+    uint64_t cap_unit;          /* instructions of one compiled command, edges staged x8 (0: 1<<18) */
     void* arena;                /* caller-owned device memory, or NULL */
     uint64_t arena_bytes;
     void* stream;               /* hipStream_t, or NULL */
@@ -194,6 +194,8 @@ typedef struct ig_stats {
     uint64_t digest_edges;
     uint64_t commands_analysed;
     uint64_t launches;
+    double phase_us[16];       /* device time per analysis phase (profiling builds; else 0) */
+    uint64_t phase_count[16];
 } ig_stats;
 
 typedef struct ig_context ig_context;
@@ -260,6 +262,11 @@ ig_status ig_fetch_instructions(ig_context* ctx, ig_instruction* dst, size_t cap
 ig_status ig_fetch_bindings(ig_context* ctx, ig_binding* dst, size_t cap, size_t* n_out);
 ig_status ig_fetch_edges(ig_context* ctx, ig_edge* dst, size_t cap, size_t* n_out);
 ig_status ig_fetch_task_status(ig_context* ctx, int32_t* dst, size_t cap, size_t* n_out);
+
+/* Per-task timing from the device clock, in nanoseconds relative to the
+ * first task's intake: dst[2*i] = intake of task i began, dst[2*i+1] = its
+ * records were complete (after any lookahead holding).  cap = tasks. */
+ig_status ig_fetch_task_times(ig_context* ctx, double* dst, size_t cap, size_t* n_out);
 
 /* Per-kind counts, resizes, warnings and the three record digests, all
  * computed on the device. */

@@ -69,7 +69,8 @@ class Stats(ctypes.Structure):
                 ("warnings", ctypes.c_uint64), ("tasks_submitted", ctypes.c_uint64),
                 ("tasks_rejected", ctypes.c_uint64), ("digest_instructions", ctypes.c_uint64),
                 ("digest_bindings", ctypes.c_uint64), ("digest_edges", ctypes.c_uint64),
-                ("commands_analysed", ctypes.c_uint64), ("launches", ctypes.c_uint64)]
+                ("commands_analysed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("phase_us", ctypes.c_double * 16), ("phase_count", ctypes.c_uint64 * 16)]
 
 
 EXPORTS = [
@@ -77,7 +78,7 @@ EXPORTS = [
     "ig_buffer_destroy", "ig_submit_task", "ig_submit_tasks", "ig_epoch", "ig_shutdown",
     "ig_flush_window", "ig_batch_flush", "ig_sync", "ig_rewind", "ig_counts",
     "ig_fetch_instructions", "ig_fetch_bindings", "ig_fetch_edges", "ig_fetch_task_status",
-    "ig_stats_get", "ig_status_str",
+    "ig_fetch_task_times", "ig_stats_get", "ig_status_str",
 ]
 
 _libs: Dict[str, ctypes.CDLL] = {}
@@ -108,6 +109,7 @@ def lib(path: Optional[str] = None) -> ctypes.CDLL:
     L.ig_counts.argtypes = [vp] + [P(ctypes.c_uint64)] * 4
     for n in ("ig_fetch_instructions", "ig_fetch_bindings", "ig_fetch_edges", "ig_fetch_task_status"):
         getattr(L, n).argtypes = [vp, vp, ctypes.c_size_t, P(ctypes.c_size_t)]
+    L.ig_fetch_task_times.argtypes = [vp, P(ctypes.c_double), ctypes.c_size_t, P(ctypes.c_size_t)]
     L.ig_stats_get.argtypes = [vp, P(Stats)]
     L.ig_status_str.argtypes = [ctypes.c_int32]
     L.ig_status_str.restype = ctypes.c_char_p
@@ -287,6 +289,17 @@ class Context:
             status=self._fetch(self.L.ig_fetch_task_status, np.dtype("<i4"), nt),
         )
 
+    def task_times_ns(self) -> np.ndarray:
+        """(n_tasks, 2): intake start and completion of each task, ns."""
+        nt = self.counts()[3]
+        arr = np.zeros((nt, 2), dtype=np.float64)
+        got = ctypes.c_size_t()
+        st = self.L.ig_fetch_task_times(self.h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nt,
+                                        ctypes.byref(got))
+        if st != 0:
+            raise IgError("ig_fetch_task_times", st)
+        return arr[: got.value]
+
     def stats(self) -> Dict[str, object]:
         s = Stats()
         st = self.L.ig_stats_get(self.h, ctypes.byref(s))
@@ -295,6 +308,8 @@ class Context:
         out = {k: getattr(s, k) for k, _ in Stats._fields_}
         out["per_kind"] = list(s.per_kind)
         out["per_dep"] = list(s.per_dep)
+        out["phase_us"] = list(s.phase_us)
+        out["phase_count"] = list(s.phase_count)
         return out
 
     def close(self):

@@ -64,7 +64,7 @@ static bool make_caps(const ig_context_desc* d, Caps& k) {
     k.flush_horizons = d->flush_horizons ? d->flush_horizons : 2;
     k.queue_cap = d->queue_cap;
     k.threads = d->threads ? d->threads : 256;
-    if (k.threads < 32 || k.threads > MAX_THREADS || (k.threads & 31)) return false;
+    if (k.threads < 64 || k.threads > MAX_THREADS || (k.threads & 63)) return false;
     k.n_workers = std::min(k.threads, k.n_mem);
     k.cap_cmds = (u32)(d->cap_commands ? d->cap_commands : 65536);
     k.cap_instr = d->cap_instructions ? d->cap_instructions : (1ull << 20);
@@ -121,6 +121,9 @@ static u64 carve(const Caps& k, char* base, DevCtx* h, Tail* tail = nullptr) {
     TAKE(b_alloc, u32, k.cap_binds);
     TAKE(has_succ, u8, k.cap_instr);
     TAKE(task_status, i32, k.cap_cmds);
+    TAKE(task_t0, u64, k.cap_cmds);
+    TAKE(task_t1, u64, k.cap_cmds);
+    TAKE(phase, u64, 32);
     TAKE(bufs, DBuf, MAX_BUF);
     TAKE(allocs, DAlloc, k.cap_allocs);
     TAKE(live_n, u32, bm);
@@ -279,7 +282,8 @@ ig_status ig_context_create(const ig_context_desc* desc, ig_context** out) {
     c->dstats = tail.dstats;
     c->pack = tail.pack;
     fill_config(k, c->h);
-    if (igrt::copy_h2d(c->dctx, &c->h, sizeof(DevCtx), c->stream) != 0 ||
+    if (igrt::memset_d(c->h.phase, 0, 32 * sizeof(u64), c->stream) != 0 ||
+        igrt::copy_h2d(c->dctx, &c->h, sizeof(DevCtx), c->stream) != 0 ||
         igrt::copy_h2d(c->dptrs, &c->dctx, sizeof(DevCtx*), c->stream) != 0 ||
         igrt::stream_sync(c->stream) != 0) {
         if (c->own_arena) igrt::dev_free(c->arena);
@@ -497,6 +501,7 @@ ig_status ig_rewind(ig_context* c) {
     Scalars z;
     std::memset(&z, 0, sizeof z);
     if (igrt::memset_d(&c->dctx->s, 0, sizeof(Scalars), c->stream) != 0) return IG_E_DEVICE;
+    if (igrt::memset_d(c->h.phase, 0, 32 * sizeof(u64), c->stream) != 0) return IG_E_DEVICE;
     c->cur_i = c->cur_b = c->cur_e = c->cur_t = 0;
     c->s = z;
     c->s_valid = false;
@@ -555,6 +560,28 @@ ig_status ig_fetch_task_status(ig_context* c, int32_t* dst, size_t cap, size_t* 
     return IG_OK;
 }
 
+ig_status ig_fetch_task_times(ig_context* c, double* dst, size_t cap, size_t* n_out) {
+    if (!c || (!dst && cap)) return IG_E_INVALID;
+    const ig_status st = refresh(c);
+    if (st != IG_OK) return st;
+    const u64 n = std::min<u64>(cap, c->s.n_tasks);
+    std::vector<u64> t0(n), t1(n);
+    if (n) {
+        if (igrt::copy_d2h(t0.data(), c->h.task_t0, n * sizeof(u64), c->stream) != 0 ||
+            igrt::copy_d2h(t1.data(), c->h.task_t1, n * sizeof(u64), c->stream) != 0 ||
+            igrt::stream_sync(c->stream) != 0)
+            return IG_E_DEVICE;
+    }
+    const double khz = igrt::clock_khz();
+    if (khz <= 0) return IG_E_DEVICE;
+    for (u64 i = 0; i < n; ++i) {
+        dst[2 * i] = (double)(t0[i] - t0[0]) / khz * 1e6;
+        dst[2 * i + 1] = (double)(t1[i] - t0[0]) / khz * 1e6;
+    }
+    if (n_out) *n_out = (size_t)n;
+    return IG_OK;
+}
+
 ig_status ig_stats_get(ig_context* c, ig_stats* out) {
     if (!c || !out) return IG_E_INVALID;
     ig_status st = refresh(c);
@@ -580,6 +607,14 @@ ig_status ig_stats_get(ig_context* c, ig_stats* out) {
     out->digest_edges = ds.digest[2];
     out->commands_analysed = c->s.cmd_next;
     out->launches = c->launches;
+    u64 ph[32];
+    if (igrt::copy_d2h(ph, c->h.phase, sizeof ph, c->stream) != 0 || igrt::stream_sync(c->stream) != 0)
+        return IG_E_DEVICE;
+    const double khz = igrt::clock_khz();
+    for (int i = 0; i < 16; ++i) {
+        out->phase_us[i] = khz > 0 ? (double)ph[i] / khz * 1e3 : 0.0;
+        out->phase_count[i] = ph[16 + i];
+    }
     return IG_OK;
 }
 

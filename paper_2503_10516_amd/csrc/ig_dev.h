@@ -51,11 +51,13 @@ struct ThreadCtx {
 };
 extern thread_local ThreadCtx cur;
 void barrier_wait(Barrier* b, int line);
+unsigned shfl_up(unsigned v, unsigned delta);  // 64-lane wave shuffle, emulated
 }  // namespace igsim
 inline unsigned ig_tid() { return igsim::cur.tid; }
 inline unsigned ig_nthreads() { return igsim::cur.nthreads; }
 inline unsigned ig_block() { return igsim::cur.block; }
 inline void ig_barrier_at(int line) { igsim::barrier_wait(igsim::cur.bar, line); }
+inline unsigned ig_shfl_up(unsigned v, unsigned delta) { return igsim::shfl_up(v, delta); }
 inline unsigned atomicAdd(unsigned* p, unsigned v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v) {
     return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
@@ -64,6 +66,7 @@ inline unsigned long long atomicOr(unsigned long long* p, unsigned long long v) 
     return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST);
 }
 inline unsigned atomicOr(unsigned* p, unsigned v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+inline unsigned atomicExch(unsigned* p, unsigned v) { return __atomic_exchange_n(p, v, __ATOMIC_SEQ_CST); }
 inline unsigned atomicCAS(unsigned* p, unsigned cmp, unsigned v) {
     __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
     return cmp;
@@ -73,6 +76,7 @@ inline unsigned long long atomicCAS(unsigned long long* p, unsigned long long cm
     return cmp;
 }
 inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+unsigned long long ig_clock();
 #define IGD inline
 #define IGN
 #else
@@ -81,6 +85,8 @@ __device__ __forceinline__ unsigned ig_tid() { return threadIdx.x; }
 __device__ __forceinline__ unsigned ig_nthreads() { return blockDim.x; }
 __device__ __forceinline__ unsigned ig_block() { return blockIdx.x; }
 __device__ __forceinline__ void ig_barrier_at(int) { __syncthreads(); }
+__device__ __forceinline__ unsigned long long ig_clock() { return wall_clock64(); }
+__device__ __forceinline__ unsigned ig_shfl_up(unsigned v, unsigned delta) { return __shfl_up(v, delta, 64); }
 #define IGD __device__ __forceinline__
 #define IGN __device__ __noinline__
 #endif
@@ -127,8 +133,8 @@ struct DBuf {
     u32 pm_off;     // u32[ncells]   producer memory
     u32 mask_off;   // u64[ncells*mw] up-to-date memories
     u32 init_off;   // u32[ncells]   initialised (Sec. 4.4)
+    u32 uninit;     // cells not yet initialised (0: the whole buffer is)
     u32 stamp_off;  // u64[ncells]   overlapping-write detection: (task+1)<<32 | chunk
-    u32 pad;
 };
 
 struct DAlloc {
@@ -215,6 +221,9 @@ struct DevCtx {
     u32* b_alloc;
     u8* has_succ;
     i32* task_status;
+    u64* task_t0;   // [cap_cmds] device clock when the task's intake began
+    u64* task_t1;   // [cap_cmds] device clock when its records were complete
+    u64* phase;     // [32] device-clock ticks per analysis phase (profiling builds only)
     // --- state ---
     DBuf* bufs;       // [MAX_BUF]
     DAlloc* allocs;   // [cap_allocs]
@@ -284,6 +293,7 @@ int copy_h2d(void* dst, const void* src, size_t bytes, void* stream);
 int copy_d2h(void* dst, const void* src, size_t bytes, void* stream);
 int memset_d(void* dst, int v, size_t bytes, void* stream);
 int stream_sync(void* stream);
+double clock_khz();
 int launch_analyse(igd::DevCtx* const* dev_ctx_ptrs_device, unsigned n_blocks, unsigned threads, void* stream);
 int launch_pack_instructions(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_instruction* out_dev,
                              void* stream);

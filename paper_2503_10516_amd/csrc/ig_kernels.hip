@@ -26,8 +26,8 @@ namespace igd {
 // ===========================================================================
 struct Shared {
     Scalars s;
-    u32 scan[MAX_THREADS];
-    u32 scan_tmp[MAX_THREADS];
+    u32 scan[MAX_THREADS / 64];
+    u32 scan_tmp[16];
     u32 total;
     u32 flag;        // generic OR flag
     u32 flag2;
@@ -37,11 +37,13 @@ struct Shared {
     u32 copy_top;    // coherence copies found for that task
     u32 nfree;       // allocations freed in the allocation phase
     u32 t_dims, t_nacc, t_id, t_cmd;
+    u32 t_stamps;  // some write may leave its chunk's dim-0 range: check overlaps cell by cell
     i64 t_lo[3], t_hi[3];
     u32 n_alloc_instr, n_new_allocs, n_copies, n_kernels;
     u32 win_first, win_n;  // lookahead window (queue positions)
     u32 do_horizon;
     u32 miss_total;
+    u64 tick;
 };
 
 IGD u32 tid() { return ig_tid(); }
@@ -59,6 +61,27 @@ IGD bool failed(Shared& sh) {
     return e;
 }
 
+// Phase profile (IG_PHASE_PROFILE builds): device-clock ticks spent since the
+// previous checkpoint are charged to phase `id`.
+enum Phase : u32 {
+    PH_INTAKE_REGIONS, PH_INTAKE_CHECKS, PH_LOOKAHEAD, PH_COMPILE_REGIONS, PH_ALLOC, PH_COH_COUNT, PH_SCANS,
+    PH_COH_EMIT, PH_INBOX, PH_KERNELS, PH_EDGES_OUT, PH_SYNC, PH_OTHER, PH_N
+};
+IGD void tick(DevCtx& c, Shared& sh, u32 id) {
+#ifdef IG_PHASE_PROFILE
+    if (tid() == 0) {
+        const u64 now = ig_clock();
+        c.phase[id] += now - sh.tick;
+        c.phase[16 + id] += 1;
+        sh.tick = now;
+    }
+#else
+    (void)c;
+    (void)sh;
+    (void)id;
+#endif
+}
+
 // Uniform read of a word that threads may have just written (first barrier)
 // and that one thread may change right after (second barrier).
 IGD u32 uniform(const u32& v) {
@@ -69,8 +92,36 @@ IGD u32 uniform(const u32& v) {
 }
 
 // ===========================================================================
-// Block-wide exclusive scan of a u32 array in global memory; returns total.
+// Scans: inclusive scan inside each 64-lane wave with shuffles, wave totals
+// through LDS (one barrier).  The workgroup size is a multiple of 64.
 // ===========================================================================
+IGD u32 wave_incl_scan(u32 v) {
+    const u32 lane = tid() & 63;
+    for (u32 off = 1; off < 64; off <<= 1) {
+        const u32 y = ig_shfl_up(v, off);
+        if (lane >= off) v += y;
+    }
+    return v;
+}
+
+// exclusive prefix of per-thread values over the workgroup; *total = sum
+IGD u32 block_excl(Shared& sh, u32 v, u32* total) {
+    const u32 incl = wave_incl_scan(v);
+    const u32 w = tid() >> 6, nw = nt() >> 6;
+    if ((tid() & 63) == 63) sh.scan[w] = incl;
+    bar();
+    u32 base = 0, all = 0;
+    for (u32 i = 0; i < nw; ++i) {
+        const u32 x = sh.scan[i];
+        if (i < w) base += x;
+        all += x;
+    }
+    bar();
+    *total = all;
+    return base + incl - v;
+}
+
+// Block-wide exclusive scan of a u32 array in global memory; returns total.
 IGN u32 block_exscan(Shared& sh, u32* a, u32 n) {
     const u32 T = nt(), t = tid();
     const u32 per = (n + T - 1) / T;
@@ -78,26 +129,15 @@ IGN u32 block_exscan(Shared& sh, u32* a, u32 n) {
     const u32 hi = lo + per < n ? lo + per : n;
     u32 sum = 0;
     for (u32 i = lo; i < hi; ++i) sum += a[i];
-    sh.scan[t] = sum;
-    bar();
-    // Hillis-Steele inclusive scan over the per-thread sums
-    for (u32 off = 1; off < T; off <<= 1) {
-        u32 v = sh.scan[t];
-        if (t >= off) v += sh.scan[t - off];
-        bar();
-        sh.scan[t] = v;
-        bar();
-    }
-    const u32 incl = sh.scan[t];
-    if (t == T - 1) sh.total = incl;
-    u32 run = incl - sum;
+    u32 total;
+    u32 run = block_excl(sh, sum, &total);
     for (u32 i = lo; i < hi; ++i) {
-        u32 v = a[i];
+        const u32 v = a[i];
         a[i] = run;
         run += v;
     }
     bar();
-    return sh.total;
+    return total;
 }
 
 // ===========================================================================
@@ -679,6 +719,7 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
                 B.n[d] = newn[d];
             }
             B.ncells = nc;
+            B.uninit = 0;
             B.prod_off = heap_alloc(c, sh, nc);
             B.pm_off = heap_alloc(c, sh, nc);
             B.mask_off = heap_alloc(c, sh, 2 * nc * c.mw);
@@ -722,7 +763,9 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
         W32(c, B.prod_off)[cell] = W32(c, sh.scan_tmp[1])[oc];
         W32(c, B.pm_off)[cell] = W32(c, sh.scan_tmp[2])[oc];
         for (u32 w = 0; w < c.mw; ++w) W64(c, B.mask_off)[cell * c.mw + w] = W64(c, sh.scan_tmp[3])[oc * c.mw + w];
-        W32(c, B.init_off)[cell] = W32(c, sh.scan_tmp[4])[oc];
+        const u32 iv = W32(c, sh.scan_tmp[4])[oc];
+        W32(c, B.init_off)[cell] = iv;
+        if (!iv) atomicAdd(&B.uninit, 1u);
         W64(c, B.stamp_off)[cell] = W64(c, sh.scan_tmp[5])[oc];
     }
     // --- allocation maps: each by the owner of its memory ---
@@ -841,6 +884,7 @@ IGN void unit_end(DevCtx& c, Shared& sh) {
 // every instruction since the last horizon/epoch without a successor.
 // ===========================================================================
 IGN void compile_sync(DevCtx& c, Shared& sh, bool epoch) {
+    tick(c, sh, PH_OTHER);
     if ((u64)sh.s.n_instr + 1 > c.cap_instr) {
         if (tid() == 0) set_error(sh, IG_E_CAPACITY);
         bar();
@@ -852,24 +896,14 @@ IGN void compile_sync(DevCtx& c, Shared& sh, bool epoch) {
     const u32 a = lo + (t * per < n ? t * per : n), e = (a + per < x) ? a + per : x;
     u32 cnt = 0;
     for (u32 i = a; i < e; ++i) cnt += c.has_succ[i] ? 0 : 1;
-    sh.scan[t] = cnt;
-    bar();
-    for (u32 off = 1; off < T; off <<= 1) {
-        u32 v = sh.scan[t];
-        if (t >= off) v += sh.scan[t - off];
-        bar();
-        sh.scan[t] = v;
-        bar();
-    }
-    if (t == T - 1) sh.total = sh.scan[t];
-    bar();
-    const u32 total = sh.total;
+    u32 total;
+    const u32 excl = block_excl(sh, cnt, &total);
     if ((u64)sh.s.n_edges + total > c.cap_edges) {
         if (t == 0) set_error(sh, IG_E_CAPACITY);
         bar();
         return;
     }
-    u64 o = sh.s.n_edges + sh.scan[t] - cnt;
+    u64 o = sh.s.n_edges + excl;
     for (u32 i = a; i < e; ++i)
         if (!c.has_succ[i]) {
             c.e_from[o] = i;
@@ -895,6 +929,7 @@ IGN void compile_sync(DevCtx& c, Shared& sh, bool epoch) {
         sh.s.last_sync = x;
     }
     bar();
+    tick(c, sh, PH_SYNC);
 }
 
 // ===========================================================================
@@ -1526,20 +1561,38 @@ IGN void load_task(DevCtx& c, Shared& sh, u32 ci) {
             sh.t_lo[d] = cmd.task.box.min[d];
             sh.t_hi[d] = cmd.task.box.max[d];
         }
+        // Writes through one_to_one, slice(d > 0) or a neighborhood without a
+        // dim-0 radius stay inside their chunk's dim-0 range; chunks partition
+        // that range, so such writes of different chunks cannot overlap.
+        u32 stamps = 0;
+        for (u32 j = 0; j < cmd.task.n_access; ++j) {
+            const ig_access& a = cmd.task.access[j];
+            if (!(a.mode & IG_WRITE)) continue;
+            const bool confined = a.mapper == IG_MAP_ONE_TO_ONE || (a.mapper == IG_MAP_SLICE && a.slice_dim != 0) ||
+                                  (a.mapper == IG_MAP_NEIGHBORHOOD && a.radius[0] == 0);
+            if (!confined) stamps = 1;
+        }
+        sh.t_stamps = stamps;
     }
     bar();
 }
 
-IGN void compile_task(DevCtx& c, Shared& sh, u32 ci) {
-    load_task(c, sh, ci);
-    compute_regions(c, sh);
+IGN void compile_task(DevCtx& c, Shared& sh, u32 ci, bool fresh) {
+    tick(c, sh, PH_LOOKAHEAD);
+    if (!fresh) {
+        load_task(c, sh, ci);
+        compute_regions(c, sh);
+    }
     unit_begin(c, sh);
+    tick(c, sh, PH_COMPILE_REGIONS);
     alloc_phase(c, sh);
     if (failed(sh)) return;
+    tick(c, sh, PH_ALLOC);
     for (u32 i = tid(); i < c.n_mem; i += nt()) c.inbox_cnt[i] = 0;
     bar();
     coherence_count(c, sh);
     if (failed(sh)) return;
+    tick(c, sh, PH_COH_COUNT);
     // scans: copies and kernels per device, inbox slots per memory
     for (u32 i = tid(); i < c.n_dev; i += nt()) {
         c.dev_base[i] = c.dev_cnt[i];
@@ -1560,17 +1613,25 @@ IGN void compile_task(DevCtx& c, Shared& sh, u32 ci) {
     if (failed(sh)) return;
     const u32 copy_first = sh.unit_first + sh.unit_n;
     const u32 kern_first = copy_first + n_copies;
+    tick(c, sh, PH_SCANS);
     coherence_emit(c, sh, copy_first);
     bar();
+    tick(c, sh, PH_COH_EMIT);
     inbox_drain(c, sh);
     bar();
+    tick(c, sh, PH_INBOX);
     kernels_emit(c, sh, kern_first);
     bar();
+    tick(c, sh, PH_KERNELS);
     if (tid() == 0) sh.unit_n += n_copies + n_kernels;
     bar();
     unit_end(c, sh);
-    if (tid() == 0) sh.s.n_binds += (u64)n_kernels * sh.t_nacc;
+    if (tid() == 0) {
+        sh.s.n_binds += (u64)n_kernels * sh.t_nacc;
+        c.task_t1[sh.t_id] = ig_clock();
+    }
     bar();
+    tick(c, sh, PH_EDGES_OUT);
 }
 
 // ===========================================================================
@@ -1660,11 +1721,12 @@ IGN void plan_merge(DevCtx& c, Shared& sh) {
     bar();
 }
 
-IGN void compile_entry(DevCtx& c, Shared& sh, u32 entry) {
+// fresh: the regions of this task are still in c.reg (compiled right after intake)
+IGN void compile_entry(DevCtx& c, Shared& sh, u32 entry, bool fresh) {
     if (entry & 0x80000000u) {
         compile_sync(c, sh, false);
     } else {
-        compile_task(c, sh, entry);
+        compile_task(c, sh, entry, fresh);
     }
 }
 
@@ -1676,7 +1738,7 @@ IGN void flush_queue(DevCtx& c, Shared& sh) {
             sh.win_n = n - i - 1;
         }
         bar();
-        compile_entry(c, sh, c.queue[i]);
+        compile_entry(c, sh, c.queue[i], false);
         bar();
     }
     const u32 NP = sh.s.n_buffers * c.n_mem;
@@ -1694,7 +1756,7 @@ IGN void push_command(DevCtx& c, Shared& sh, u32 entry, bool allocating) {
     if (!c.lookahead || (qlen == 0 && !allocating)) {
         if (tid() == 0) sh.win_n = 0;
         bar();
-        compile_entry(c, sh, entry);
+        compile_entry(c, sh, entry, !(entry & 0x80000000u));
         return;
     }
     if (allocating) plan_merge(c, sh);
@@ -1720,6 +1782,8 @@ IGN void push_command(DevCtx& c, Shared& sh, u32 entry, bool allocating) {
 // ===========================================================================
 IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
     load_task(c, sh, ci);
+    if (tid() == 0) c.task_t0[sh.t_id] = ig_clock();
+    tick(c, sh, PH_OTHER);
     if (tid() == 0) *c.miss_n = 0;
     bar();
     compute_regions(c, sh);
@@ -1730,6 +1794,7 @@ IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
         if (uniform(*c.miss_n) && tid() == 0) set_error(sh, IG_E_DEVICE);
         if (failed(sh)) return;
     }
+    tick(c, sh, PH_INTAKE_REGIONS);
     // Sec. 4.4 checks
     const u32 A = sh.t_nacc, C = c.chunks, t = sh.t_id;
     if (tid() == 0) {
@@ -1742,6 +1807,9 @@ IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
         const Region& r = c.reg[k * IG_MAX_ACCESS + j];
         if (r.empty) continue;
         const DBuf& B = c.bufs[r.buffer];
+        const bool check_read = (r.mode & IG_READ) && B.uninit != 0;
+        const bool check_write = (r.mode & IG_WRITE) && sh.t_stamps;
+        if (!check_read && !check_write) continue;
         u64* stamp = W64(c, B.stamp_off);
         const u32* init = W32(c, B.init_off);
         const u64 mine = ((u64)(t + 1) << 32) | k;
@@ -1749,8 +1817,8 @@ IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
             for (u32 i1 = r.clo[1]; i1 < r.chi[1]; ++i1)
                 for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2) {
                     const u32 cell = cell_of(B, i0, i1, i2);
-                    if ((r.mode & IG_READ) && !init[cell]) sh.flag2 = 1;
-                    if (r.mode & IG_WRITE) {
+                    if (check_read && !init[cell]) sh.flag2 = 1;
+                    if (check_write) {
                         u64 old = stamp[cell];
                         while (true) {
                             if ((old >> 32) == (u64)(t + 1)) {
@@ -1770,7 +1838,10 @@ IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
         const i32 st = overlap ? IG_E_OVERLAPPING_WRITE : (sh.flag2 ? IG_W_UNINIT_READ : IG_OK);
         c.task_status[sh.s.n_tasks] = st;
         sh.s.n_tasks += 1;
-        if (overlap) sh.s.rejected += 1;
+        if (overlap) {
+            sh.s.rejected += 1;
+            c.task_t1[sh.t_id] = ig_clock();
+        }
         if (st == IG_W_UNINIT_READ) sh.s.warnings += 1;
     }
     bar();
@@ -1779,14 +1850,18 @@ IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
         const u32 k = idx / A, j = idx % A;
         const Region& r = c.reg[k * IG_MAX_ACCESS + j];
         if (r.empty || !(r.mode & IG_WRITE)) continue;
-        const DBuf& B = c.bufs[r.buffer];
+        DBuf& B = c.bufs[r.buffer];
+        if (B.uninit == 0) continue;
         u32* init = W32(c, B.init_off);
         for (u32 i0 = r.clo[0]; i0 < r.chi[0]; ++i0)
             for (u32 i1 = r.clo[1]; i1 < r.chi[1]; ++i1)
-                for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2) init[cell_of(B, i0, i1, i2)] = 1;
+                for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2)
+                    if (atomicExch(&init[cell_of(B, i0, i1, i2)], 1u) == 0) atomicAdd(&B.uninit, 0xFFFFFFFFu);
     }
     bar();
+    tick(c, sh, PH_INTAKE_CHECKS);
     const bool allocating = c.lookahead ? task_allocating(c, sh) : false;
+    tick(c, sh, PH_LOOKAHEAD);
     push_command(c, sh, ci, allocating);
     if (failed(sh)) return;
     if (tid() == 0) {
@@ -1831,6 +1906,7 @@ IGN void create_buffer(DevCtx& c, Shared& sh, const DevCmd& cmd) {
                 W32(c, B.pm_off)[0] = cmd.init ? 0 : NONE;
                 for (u32 w = 0; w < c.mw; ++w) W64(c, B.mask_off)[w] = (cmd.init && w == 0) ? 1ull : 0ull;
                 W32(c, B.init_off)[0] = cmd.init ? 1 : 0;
+                B.uninit = cmd.init ? 0 : 1;
                 W64(c, B.stamp_off)[0] = 0;
                 for (u32 m = 0; m < c.n_mem; ++m) {
                     c.live_n[b * c.n_mem + m] = 0;
@@ -1968,7 +2044,10 @@ IGN void init_state(DevCtx& c, Shared& sh) {
 }
 
 IGN void analyse(DevCtx& c, Shared& sh) {
-    if (tid() == 0) sh.s = c.s;
+    if (tid() == 0) {
+        sh.s = c.s;
+        sh.tick = ig_clock();
+    }
     bar();
     if (uniform(sh.s.cmd_next == 0 && sh.s.n_instr == 0)) init_state(c, sh);
     while (true) {
@@ -2165,6 +2244,12 @@ int memset_d(void* dst, int v, size_t bytes, void* stream) {
     return check(hipMemsetAsync(dst, v, bytes, (hipStream_t)stream));
 }
 int stream_sync(void* stream) { return check(hipStreamSynchronize((hipStream_t)stream)); }
+double clock_khz() {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
+    return (double)khz;
+}
 int launch_analyse(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, void* stream) {
     hipLaunchKernelGGL(ig_analyse, dim3(n_blocks), dim3(threads), 0, (hipStream_t)stream, ptrs);
     return check(hipGetLastError());

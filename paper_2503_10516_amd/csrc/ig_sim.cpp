@@ -12,6 +12,12 @@
 
 #include "ig_kernels.hip"
 
+unsigned long long ig_clock() {
+    return (unsigned long long)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
 namespace igsim {
 thread_local ThreadCtx cur;
 struct Barrier {
@@ -19,6 +25,7 @@ struct Barrier {
     std::condition_variable cv;
     unsigned n = 0, count = 0, gen = 0;
     int line[1024];
+    unsigned xchg[1024];
 };
 void barrier_wait(Barrier* b, int line) {
     b->line[cur.tid] = line;
@@ -34,6 +41,15 @@ void barrier_wait(Barrier* b, int line) {
         for (unsigned t = 0; t < cur.nthreads; ++t) std::fprintf(stderr, "  thread %u last barrier at line %d\n", t, b->line[t]);
         std::abort();
     }
+}
+unsigned shfl_up(unsigned v, unsigned delta) {
+    Barrier* b = cur.bar;
+    b->xchg[cur.tid] = v;
+    barrier_wait(b, -1);
+    const unsigned lane = cur.tid % 64;
+    const unsigned r = lane >= delta ? b->xchg[cur.tid - delta] : v;
+    barrier_wait(b, -2);
+    return r;
 }
 }  // namespace igsim
 
@@ -63,6 +79,7 @@ int memset_d(void* dst, int v, size_t bytes, void*) {
     return 0;
 }
 int stream_sync(void*) { return 0; }
+double clock_khz() { return 1e6; }
 
 int launch_analyse(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, void*) {
     for (unsigned b = 0; b < n_blocks; ++b) {

@@ -81,17 +81,17 @@ SIM_SCENARIOS = [
 @pytest.mark.parametrize("name,make", SIM_SCENARIOS, ids=[s[0] for s in SIM_SCENARIOS])
 def test_sim_scenarios(name, make, sim_lib):
     s = make()
-    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=32), name)
+    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), name)
 
 
 @pytest.mark.parametrize("seed", range(0, 60, 3))
 def test_sim_random_streams(seed, sim_lib):
     s = S.random_small(seed)
-    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=32), s.name)
+    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), s.name)
 
 
 def test_sim_invalid_arguments(sim_lib):
-    ctx = B.Context(1, 2, lib_path=sim_lib, threads=32)
+    ctx = B.Context(1, 2, lib_path=sim_lib, threads=64)
     b = ctx.buffer_create(2, (8, 8, 1), 4, 1)
     with pytest.raises(B.IgError) as e:
         ctx.submit(S.Task(1, (0, 0, 0), (8, 1, 1), (S.Access(b, S.READ, S.ONE_TO_ONE),)))
@@ -99,12 +99,12 @@ def test_sim_invalid_arguments(sim_lib):
     with pytest.raises(B.IgError):
         ctx.submit(S.Task(2, (0, 0, 0), (8, 8, 1), (S.Access(5, S.READ, S.ALL),)))
     with pytest.raises(B.IgError):
-        B.Context(1, 2, chunks=3, lib_path=sim_lib, threads=32)
+        B.Context(1, 2, chunks=3, lib_path=sim_lib, threads=64)
     ctx.close()
 
 
 def test_sim_capacity_error_is_reported(sim_lib):
     s = S.stencil_1d(n=256, tasks=16)
     with pytest.raises(B.IgError) as e:
-        B.run_stream(s, lib_path=sim_lib, threads=32, cap_instructions=40)
+        B.run_stream(s, lib_path=sim_lib, threads=64, cap_instructions=40)
     assert e.value.status == B.IG_E_CAPACITY
