@@ -126,3 +126,39 @@ def test_overlapping_write_status():
     want, got = run_both(s)
     assert list(got["status"]) == [0, -2, 0]
     assert_same(want, got, "overlap")
+
+
+def test_batched_launch_matches_single_streams():
+    """One launch over many streams (one workgroup each) gives every stream
+    exactly its oracle graph."""
+    streams = [S.random_small(1000 + i) for i in range(24)] + [S.stencil_1d(n=512, tasks=20), S.nbody_example()]
+    ctxs = []
+    for s in streams:
+        ctx = B.make_context(s, threads=256)
+        ctx.record(s)
+        ctxs.append(ctx)
+    print(f"[gpu] batched launch over {len(ctxs)} streams", flush=True)
+    B.batch_flush(ctxs)
+    for s, ctx in zip(streams, ctxs):
+        assert ctx.sync() == 0
+        got = ctx.fetch_all()
+        assert_same(oracle.run_stream(s), got, "batched:" + s.name)
+        ctx.close()
+
+
+def test_batched_generator_streams_sample():
+    """Small streams of the batched workload generator, batched, against the
+    oracle (the generator's large streams are checked against single-stream
+    runs by the benchmark)."""
+    gen = [S.batched_stream(S.BATCHED_SEED, i, max_tasks=120, max_log_chunks=6, max_log_extent=14)
+           for i in range(12)]
+    ctxs = []
+    for s in gen:
+        ctx = B.make_context(s, threads=256)
+        ctx.record(s)
+        ctxs.append(ctx)
+    B.batch_flush(ctxs)
+    for s, ctx in zip(gen, ctxs):
+        assert ctx.sync() == 0
+        assert_same(oracle.run_stream(s), ctx.fetch_all(), "batchgen:" + s.name)
+        ctx.close()
