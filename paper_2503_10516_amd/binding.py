@@ -161,8 +161,14 @@ def estimate_caps(stream) -> Dict[str, int]:
             if a.mode & 1:
                 instr += C * min(C, n_dev + 1) if a.mapper in (2, 3, 4) else 6 * C
             instr += 2
+            # allocation, resize copies and free per device: every task without
+            # lookahead, tasks with fixed (possibly growing) regions with it
+            if not stream.lookahead or a.mapper == 4:
+                instr += 4 * n_dev
     instr = min(instr, 0xFFFF0000)
-    return dict(cap_commands=len(stream.cmds) + 8, cap_instructions=instr, cap_edges=6 * instr)
+    # a kernel reading a region written piecewise since the last horizon gains
+    # an edge per piece (growing read ranges), so edges get a wide margin
+    return dict(cap_commands=len(stream.cmds) + 8, cap_instructions=instr, cap_edges=10 * instr)
 
 
 class Context:

@@ -128,6 +128,8 @@ struct DBuf {
     i64 ext[3];
     u32 n[3];       // cells per dimension
     u32 bp_off[3];  // i64[n[d]+1] breakpoints
+    u32 hx_off[3];  // open-addressing hash: coordinate -> breakpoint index (i64 key, u32 value, 4 words a slot)
+    u32 hx_bits[3]; // log2 of the slot count
     u32 ncells;
     u32 prod_off;   // u32[ncells]   original producer (NONE: uninitialised)
     u32 pm_off;     // u32[ncells]   producer memory
@@ -141,9 +143,17 @@ struct DAlloc {
     u32 buffer, mem, alive, ncells;
     i64 lo[3], hi[3];   // allocation box (buffer coordinates)
     u32 clo[3], chi[3]; // the same box in grid cells
-    u32 writer_off;     // u32[ncells] last writer
-    u32 rd_off;         // u32[ncells] reader-list heads
+    u32 am_off;         // AmCell[ncells]: the allocation map, one 16-byte record per grid cell
+    u32 old_am;         // scratch for grid refinement
 };
+
+// One cell of an allocation map (Sec. 3.2/3.3 tracking): last writer, with
+// bit 31 set when the writer is the allocation's ALLOC; two inline readers;
+// the head of an overflow list of reader blocks for further readers.
+struct AmCell {
+    u32 w, r0, r1, ov;
+};
+constexpr u32 W_ALLOC = 0x80000000u;
 
 // One region of one (chunk, access) of the task being analysed.
 struct Region {
@@ -295,6 +305,7 @@ int memset_d(void* dst, int v, size_t bytes, void* stream);
 int stream_sync(void* stream);
 double clock_khz();
 int launch_analyse(igd::DevCtx* const* dev_ctx_ptrs_device, unsigned n_blocks, unsigned threads, void* stream);
+int launch_analyse_wide(igd::DevCtx* const* dev_ctx_ptrs_device, unsigned n_blocks, unsigned threads, void* stream);
 int launch_pack_instructions(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_instruction* out_dev,
                              void* stream);
 int launch_pack_bindings(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_binding* out_dev, void* stream);

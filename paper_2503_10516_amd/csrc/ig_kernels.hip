@@ -41,9 +41,12 @@ struct Shared {
     i64 t_lo[3], t_hi[3];
     u32 n_alloc_instr, n_new_allocs, n_copies, n_kernels;
     u32 win_first, win_n;  // lookahead window (queue positions)
+    u32 t_covered;         // every requirement of the current task lies in a live allocation
     u32 do_horizon;
     u32 miss_total;
     u64 tick;
+    u64 wkey[256 * 16];  // per-worker stale-cell keys of one consumer (small case)
+    u32 wval[256 * 16];
 };
 
 IGD u32 tid() { return ig_tid(); }
@@ -145,7 +148,7 @@ IGN u32 block_exscan(Shared& sh, u32* a, u32 n) {
 // Only thread 0 allocates and frees (between barriers).
 // ===========================================================================
 IGD u32 heap_alloc(DevCtx& c, Shared& sh, u32 words) {
-    u32 need = words + 2, k = 4;
+    u32 need = words + 4, k = 4;
     while ((1u << k) < need) ++k;
     u32 off;
     if (c.heap_free[k]) {
@@ -160,12 +163,12 @@ IGD u32 heap_alloc(DevCtx& c, Shared& sh, u32 words) {
         sh.s.heap_top += 1u << k;
     }
     c.heap[off] = k;
-    return off + 2;
+    return off + 4;
 }
 
 IGD void heap_release(DevCtx& c, u32 p) {
     if (!p) return;
-    const u32 off = p - 2, k = c.heap[off];
+    const u32 off = p - 4, k = c.heap[off];
     c.heap[off + 2] = c.heap_free[k];
     c.heap_free[k] = off;
 }
@@ -173,6 +176,22 @@ IGD void heap_release(DevCtx& c, u32 p) {
 IGD u32* W32(DevCtx& c, u32 off) { return c.heap + off; }
 IGD u64* W64(DevCtx& c, u32 off) { return (u64*)(c.heap + off); }
 IGD i64* WI64(DevCtx& c, u32 off) { return (i64*)(c.heap + off); }
+IGD AmCell* am_cells(DevCtx& c, const DAlloc& a) { return (AmCell*)(c.heap + a.am_off); }
+
+IGD AmCell am_load(const AmCell* p) {
+#ifdef IG_HOST_SIM
+    return *p;
+#else
+    const uint4 v = *(const uint4*)p;
+    AmCell e;
+    e.w = v.x;
+    e.r0 = v.y;
+    e.r1 = v.z;
+    e.ov = v.w;
+    return e;
+#endif
+}
+
 
 // ===========================================================================
 // Reader lists: singly linked blocks of 7 ids; owned by one memory's worker.
@@ -308,30 +327,87 @@ struct Src {
     u32 n, cap;
 };
 
-IGN u32 src_dedup(Src& s) {
-    if (s.n == 0) return 0;
-    msort64(s.buf, s.aux, s.n);
+// sort and merge duplicate ids (kinds OR-ed); returns the new length
+IGN u32 src_dedup(u64* buf, u64* aux, u32 n) {
+    if (n == 0) return 0;
+    msort64(buf, aux, n);
     u32 o = 0;
-    for (u32 i = 0; i < s.n; ++i) {
-        const u64 id = s.buf[i] >> 8;
-        if (o > 0 && (s.buf[o - 1] >> 8) == id)
-            s.buf[o - 1] |= s.buf[i] & 0xFF;
+    for (u32 i = 0; i < n; ++i) {
+        const u64 id = buf[i] >> 8;
+        if (o > 0 && (buf[o - 1] >> 8) == id)
+            buf[o - 1] |= buf[i] & 0xFF;
         else
-            s.buf[o++] = s.buf[i];
+            buf[o++] = buf[i];
     }
-    s.n = o;
     return o;
 }
 
 IGD void src_add(Shared& sh, Src& s, u32 id, u32 kind) {
     if (s.n == s.cap) {
-        src_dedup(s);
+        s.n = src_dedup(s.buf, s.aux, s.n);
         if (s.n == s.cap) {
             set_error(sh, IG_E_CAPACITY);
             return;
         }
     }
     s.buf[s.n++] = ((u64)id << 8) | kind;
+}
+
+// The sources of one instruction: up to 16 in registers (sorted by id, kinds
+// OR-ed), spilling to the worker's global list beyond that.
+constexpr u32 REG_SRC = 16;
+struct SrcSet {
+    u64 r[REG_SRC];
+    u32 n;
+    bool spilled;
+    Src g;
+};
+
+IGD Src worker_src(DevCtx& c);
+
+IGD void ss_init(DevCtx& c, SrcSet& s) {
+    s.n = 0;
+    s.spilled = false;
+    s.g = worker_src(c);
+}
+
+IGD void ss_add(Shared& sh, SrcSet& s, u32 id, u32 kind) {
+    if (s.spilled) {
+        src_add(sh, s.g, id, kind);
+        return;
+    }
+    bool found = false;
+#pragma unroll
+    for (u32 i = 0; i < REG_SRC; ++i)
+        if (i < s.n && (u32)(s.r[i] >> 8) == id) {
+            s.r[i] |= kind;
+            found = true;
+        }
+    if (found) return;
+    if (s.n == REG_SRC) {
+#pragma unroll
+        for (u32 i = 0; i < REG_SRC; ++i) s.g.buf[i] = s.r[i];
+        s.g.n = REG_SRC;
+        s.spilled = true;
+        src_add(sh, s.g, id, kind);
+        return;
+    }
+    u64 x = ((u64)id << 8) | kind;
+    bool shifting = false;  // past the insertion point: shift everything
+#pragma unroll
+    for (u32 i = 0; i < REG_SRC; ++i) {
+        if (i < s.n) {
+            if (shifting || s.r[i] > x) {
+                shifting = true;
+                const u64 t = s.r[i];
+                s.r[i] = x;
+                x = t;
+            }
+        } else if (i == s.n) {
+            s.r[i] = x;
+        }
+    }
+    s.n += 1;
 }
 
 IGD Src worker_src(DevCtx& c) {
@@ -345,21 +421,48 @@ IGD Src worker_src(DevCtx& c) {
 
 // Stage the edges of instruction x (sources sorted by id, kinds OR-ed).  An
 // instruction without any dependency waits for the synchronisation point.
-IGN void stage(DevCtx& c, Shared& sh, u32 x, Src& s) {
-    if (s.n == 0) s.buf[s.n++] = ((u64)sh.s.S << 8) | IG_DEP_SYNC;
-    const u32 n = src_dedup(s);
-    const u32 off = atomicAdd(&sh.stage_top, n);
+IGN void stage_global(DevCtx& c, Shared& sh, u32 x, u64* buf, u64* aux, u32 n0) {
     const u32 slot = x - sh.unit_first;
+    const u32 n = src_dedup(buf, aux, n0);
+    const u32 off = atomicAdd(&sh.stage_top, n);
     if ((u64)off + n > (u64)c.cap_unit * 8 || slot >= c.cap_unit) {
         set_error(sh, IG_E_CAPACITY);
         return;
     }
     for (u32 i = 0; i < n; ++i) {
-        const u32 from = (u32)(s.buf[i] >> 8);
+        const u32 from = (u32)(buf[i] >> 8);
         c.stage_from[off + i] = from;
-        c.stage_kind[off + i] = (u8)(s.buf[i] & 0xFF);
+        c.stage_kind[off + i] = (u8)(buf[i] & 0xFF);
         c.has_succ[from] = 1;
     }
+    c.tab_off[slot] = off;
+    c.tab_cnt[slot] = n;
+}
+
+IGD void stage(DevCtx& c, Shared& sh, u32 x, SrcSet& s) {
+    if (s.spilled) {
+        stage_global(c, sh, x, s.g.buf, s.g.aux, s.g.n);
+        return;
+    }
+    const u32 slot = x - sh.unit_first;
+    if (s.n == 0) {
+        s.r[0] = ((u64)sh.s.S << 8) | IG_DEP_SYNC;
+        s.n = 1;
+    }
+    const u32 n = s.n;
+    const u32 off = atomicAdd(&sh.stage_top, n);
+    if ((u64)off + n > (u64)c.cap_unit * 8 || slot >= c.cap_unit) {
+        set_error(sh, IG_E_CAPACITY);
+        return;
+    }
+#pragma unroll
+    for (u32 i = 0; i < REG_SRC; ++i)
+        if (i < n) {
+            const u32 from = (u32)(s.r[i] >> 8);
+            c.stage_from[off + i] = from;
+            c.stage_kind[off + i] = (u8)(s.r[i] & 0xFF);
+            c.has_succ[from] = 1;
+        }
     c.tab_off[slot] = off;
     c.tab_cnt[slot] = n;
 }
@@ -401,6 +504,44 @@ IGD u32 bp_find(const i64* a, u32 n, i64 x) {  // exact index or NONE
             hi = mid;
     }
     return (lo < n && a[lo] == x) ? lo : NONE;
+}
+
+// Coordinate -> breakpoint index through the grid's hash (1-2 probes).
+constexpr i64 HX_EMPTY = (i64)0x8000000000000000ull;
+IGD u32 hx_slot(i64 x, u32 bits) { return (u32)(((u64)x * 0x9E3779B97F4A7C15ull) >> (64 - bits)); }
+
+IGD u32 hx_find(DevCtx& c, const DBuf& B, u32 d, i64 x) {
+    const u32 bits = B.hx_bits[d], mask = (1u << bits) - 1;
+    const u32* t = c.heap + B.hx_off[d];
+    for (u32 h = hx_slot(x, bits);; h = (h + 1) & mask) {
+        const i64 k = *(const i64*)(t + 4 * h);
+        if (k == x) return t[4 * h + 2];
+        if (k == HX_EMPTY) return NONE;
+    }
+}
+
+IGD u32 heap_alloc(DevCtx& c, Shared& sh, u32 words);
+IGD void heap_release(DevCtx& c, u32 p);
+
+// (thread 0) rebuild the hash of dimension d after its breakpoints changed
+IGN void hx_build(DevCtx& c, Shared& sh, DBuf& B, u32 d) {
+    heap_release(c, B.hx_off[d]);
+    const u32 n = B.n[d] + 1;
+    u32 bits = 2;
+    while ((1u << bits) < 2 * n) ++bits;
+    B.hx_bits[d] = bits;
+    B.hx_off[d] = heap_alloc(c, sh, 4u << bits);
+    if (!B.hx_off[d]) return;
+    u32* t = c.heap + B.hx_off[d];
+    for (u32 h = 0; h < (1u << bits); ++h) *(i64*)(t + 4 * h) = HX_EMPTY;
+    const i64* bp = (const i64*)(c.heap + B.bp_off[d]);
+    const u32 mask = (1u << bits) - 1;
+    for (u32 i = 0; i < n; ++i) {
+        u32 h = hx_slot(bp[i], bits);
+        while (*(i64*)(t + 4 * h) != HX_EMPTY) h = (h + 1) & mask;
+        *(i64*)(t + 4 * h) = bp[i];
+        t[4 * h + 2] = i;
+    }
 }
 
 IGD u32 cell_of(const DBuf& B, u32 i0, u32 i1, u32 i2) { return (i0 * B.n[1] + i1) * B.n[2] + i2; }
@@ -616,16 +757,15 @@ IGD u32 live_containing_cell(DevCtx& c, u32 b, u32 m, u32 i0, u32 i1, u32 i2) {
 IGN void compute_regions(DevCtx& c, Shared& sh) {
     const ig_task_desc& td = c.cmds[sh.t_cmd].task;
     const u32 C = c.chunks, A = sh.t_nacc;
-    for (u32 k = tid(); k < C; k += nt()) chunk_range(c, sh.t_lo[0], sh.t_hi[0], k, c.chunk_lo[k], c.chunk_hi[k]);
-    bar();
     for (u32 idx = tid(); idx < C * A; idx += nt()) {
         const u32 k = idx / A, j = idx % A;
         Region& r = c.reg[k * IG_MAX_ACCESS + j];
         const ig_access& a = td.access[j];
         r.buffer = a.buffer;
         r.mode = a.mode;
-        i64 clo[3] = {c.chunk_lo[k], sh.t_lo[1], sh.t_lo[2]};
-        i64 chi[3] = {c.chunk_hi[k], sh.t_hi[1], sh.t_hi[2]};
+        i64 clo[3] = {0, sh.t_lo[1], sh.t_lo[2]};
+        i64 chi[3] = {0, sh.t_hi[1], sh.t_hi[2]};
+        chunk_range(c, sh.t_lo[0], sh.t_hi[0], k, clo[0], chi[0]);
         r.empty = box_empty(clo, chi) ? 1u : 0u;
         if (!r.empty) {
             const DBuf& B = c.bufs[a.buffer];
@@ -633,9 +773,8 @@ IGN void compute_regions(DevCtx& c, Shared& sh) {
             r.empty = box_empty(r.lo, r.hi) ? 1u : 0u;
             if (!r.empty)
                 for (u32 d = 0; d < 3; ++d) {
-                    const i64* bp = bps(c, B, d);
-                    const u32 a0 = bp_find(bp, B.n[d] + 1, r.lo[d]);
-                    const u32 a1 = bp_find(bp, B.n[d] + 1, r.hi[d]);
+                    const u32 a0 = hx_find(c, B, d, r.lo[d]);
+                    const u32 a1 = hx_find(c, B, d, r.hi[d]);
                     r.clo[d] = a0;
                     r.chi[d] = a1;
                     if (a0 == NONE || a1 == NONE) {
@@ -717,6 +856,7 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
                 heap_release(c, B.bp_off[d]);
                 B.bp_off[d] = newoff[d];
                 B.n[d] = newn[d];
+                hx_build(c, sh, B, d);
             }
             B.ncells = nc;
             B.uninit = 0;
@@ -740,11 +880,9 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
                         a.clo[d] = bp_find(bps(c, B, d), B.n[d] + 1, a.lo[d]);
                         a.chi[d] = bp_find(bps(c, B, d), B.n[d] + 1, a.hi[d]);
                     }
-                    sv.buffer = a.writer_off;
-                    sv.mode = a.rd_off;
+                    sv.buffer = a.am_off;
                     a.ncells = (a.chi[0] - a.clo[0]) * (a.chi[1] - a.clo[1]) * (a.chi[2] - a.clo[2]);
-                    a.writer_off = heap_alloc(c, sh, a.ncells);
-                    a.rd_off = heap_alloc(c, sh, a.ncells);
+                    a.am_off = heap_alloc(c, sh, 4 * a.ncells);
                 }
             }
             sh.scan_tmp[9] = na;
@@ -776,31 +914,25 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
         if (owner_of(a.mem) != tid()) continue;
         const Region& sv = c.reg[s];
         const u32 on1a = sv.chi[1] - sv.clo[1], on2a = sv.chi[2] - sv.clo[2];
-        u32* wr = W32(c, a.writer_off);
-        u32* rd = W32(c, a.rd_off);
-        const u32* owr = W32(c, sv.buffer);
-        const u32* ord = W32(c, sv.mode);
+        AmCell* cells = am_cells(c, a);
+        AmCell* ocl = (AmCell*)(c.heap + sv.buffer);
         u32 l = 0;
         for (u32 i0 = a.clo[0]; i0 < a.chi[0]; ++i0)
             for (u32 i1 = a.clo[1]; i1 < a.chi[1]; ++i1)
                 for (u32 i2 = a.clo[2]; i2 < a.chi[2]; ++i2, ++l) {
                     const u32 ol = ((r0[i0] - sv.clo[0]) * on1a + (r1[i1] - sv.clo[1])) * on2a + (r2[i2] - sv.clo[2]);
-                    wr[l] = owr[ol];
-                    rd[l] = rd_copy(c, sh, a.mem, ord[ol]);
+                    AmCell e = am_load(ocl + ol);
+                    e.ov = rd_copy(c, sh, a.mem, e.ov);
+                    cells[l] = e;
                 }
         const u32 ocells = (sv.chi[0] - sv.clo[0]) * on1a * on2a;
-        for (u32 ol = 0; ol < ocells; ++ol) {
-            u32 h = ord[ol];
-            rd_clear(c, a.mem, &h);
-        }
+        for (u32 ol = 0; ol < ocells; ++ol)
+            if (ocl[ol].ov) rd_clear(c, a.mem, &ocl[ol].ov);
     }
     bar();
     if (tid() == 0) {
         for (u32 s = 1; s <= 5; ++s) heap_release(c, sh.scan_tmp[s]);
-        for (u32 s = 0; s < na; ++s) {
-            heap_release(c, c.reg[s].buffer);
-            heap_release(c, c.reg[s].mode);
-        }
+        for (u32 s = 0; s < na; ++s) heap_release(c, c.reg[s].buffer);
     }
     bar();
 }
@@ -1066,44 +1198,110 @@ IGD u32 absorbed_of(DevCtx& c, u32 b, u32 m, const i64* q, u32* out) {
     return n;
 }
 
-// access edges of one instruction against an allocation map, per cell
-IGD void edges_read(DevCtx& c, Shared& sh, Src& s, const DAlloc& a, u32 l) {
-    const u32 w = eff_w(sh, W32(c, a.writer_off)[l]);
-    src_add(sh, s, w, c.i_kind[w] == IG_ALLOC ? IG_DEP_LIFETIME : IG_DEP_TRUE);
+// ---------------------------------------------------------------------------
+// Allocation-map cells: edges against the state before an instruction and the
+// updates after it (owner-only).
+// ---------------------------------------------------------------------------
+// a read: dataflow edge from the last writer, lifetime if that is the ALLOC
+IGD void cell_read_edge(Shared& sh, SrcSet& s, const AmCell& e) {
+    const u32 w = e.w & ~W_ALLOC;
+    if (w < sh.s.S)
+        ss_add(sh, s, sh.s.S, IG_DEP_TRUE);
+    else
+        ss_add(sh, s, w, (e.w & W_ALLOC) ? IG_DEP_LIFETIME : IG_DEP_TRUE);
 }
 
-IGN void edges_write(DevCtx& c, Shared& sh, Src& s, const DAlloc& a, u32 l) {
+IGD void writer_edge(Shared& sh, SrcSet& s, const AmCell& e, u32 kind) {
+    const u32 w = e.w & ~W_ALLOC;
+    if (w < sh.s.S)
+        ss_add(sh, s, sh.s.S, kind);
+    else
+        ss_add(sh, s, w, (e.w & W_ALLOC) ? IG_DEP_LIFETIME : kind);
+}
+
+// a write: anti edges from the readers, else an output edge from the writer
+IGD void cell_write_edge(DevCtx& c, Shared& sh, SrcSet& s, const AmCell& e) {
     bool any = false;
-    for (u32 h = W32(c, a.rd_off)[l]; h; h = c.rb[h * 8 + 7])
+    u32 x;
+    if (e.r0 != NONE && eff_r(sh, e.r0, x)) {
+        ss_add(sh, s, x, IG_DEP_ANTI);
+        any = true;
+    }
+    if (e.r1 != NONE && eff_r(sh, e.r1, x)) {
+        ss_add(sh, s, x, IG_DEP_ANTI);
+        any = true;
+    }
+    for (u32 h = e.ov; h; h = c.rb[h * 8 + 7])
         for (u32 q = 0; q < RB_SLOTS; ++q) {
             const u32 r = c.rb[h * 8 + q];
-            u32 e;
-            if (r != NONE && eff_r(sh, r, e)) {
-                src_add(sh, s, e, IG_DEP_ANTI);
+            if (r != NONE && eff_r(sh, r, x)) {
+                ss_add(sh, s, x, IG_DEP_ANTI);
                 any = true;
             }
         }
-    if (!any) {
-        const u32 w = eff_w(sh, W32(c, a.writer_off)[l]);
-        src_add(sh, s, w, c.i_kind[w] == IG_ALLOC ? IG_DEP_LIFETIME : IG_DEP_OUTPUT);
+    if (!any) writer_edge(sh, s, e, IG_DEP_OUTPUT);
+}
+
+IGD void cell_free_edges(DevCtx& c, Shared& sh, SrcSet& s, const AmCell& e) {
+    const u32 w = e.w & ~W_ALLOC;
+    ss_add(sh, s, w < sh.s.S ? sh.s.S : w, IG_DEP_LIFETIME);
+    u32 x;
+    if (e.r0 != NONE && eff_r(sh, e.r0, x)) ss_add(sh, s, x, IG_DEP_LIFETIME);
+    if (e.r1 != NONE && eff_r(sh, e.r1, x)) ss_add(sh, s, x, IG_DEP_LIFETIME);
+    for (u32 h = e.ov; h; h = c.rb[h * 8 + 7])
+        for (u32 q = 0; q < RB_SLOTS; ++q) {
+            const u32 r = c.rb[h * 8 + q];
+            if (r != NONE && eff_r(sh, r, x)) ss_add(sh, s, x, IG_DEP_LIFETIME);
+        }
+}
+
+// readers gain x (inline slots first; slots whose reader reads as absent or
+// duplicates the other slot's synchronisation point are reused)
+IGD void cell_add_reader(DevCtx& c, Shared& sh, u32 m, AmCell* p, u32 x) {
+    AmCell e = am_load(p);
+    if (e.r0 != NONE && e.r0 < sh.s.E) e.r0 = NONE;
+    if (e.r1 != NONE && e.r1 < sh.s.E) e.r1 = NONE;
+    if (e.r0 != NONE && e.r1 != NONE && e.r0 < sh.s.S && e.r1 < sh.s.S) e.r1 = NONE;
+    if (e.r0 == NONE) {
+        p->r0 = x;
+        p->r1 = e.r1;
+    } else if (e.r1 == NONE) {
+        p->r0 = e.r0;
+        p->r1 = x;
+    } else {
+        rd_append(c, sh, m, &p->ov, x);
     }
 }
 
-IGN void free_edges(DevCtx& c, Shared& sh, Src& s, const DAlloc& a) {
-    for (u32 l = 0; l < a.ncells; ++l) {
-        src_add(sh, s, eff_w(sh, W32(c, a.writer_off)[l]), IG_DEP_LIFETIME);
-        for (u32 h = W32(c, a.rd_off)[l]; h; h = c.rb[h * 8 + 7])
-            for (u32 q = 0; q < RB_SLOTS; ++q) {
-                const u32 r = c.rb[h * 8 + q];
-                u32 e;
-                if (r != NONE && eff_r(sh, r, e)) src_add(sh, s, e, IG_DEP_LIFETIME);
-            }
+// a write: new last writer, no readers
+IGD void cell_set_writer(DevCtx& c, u32 m, AmCell* p, u32 w) {
+    const u32 ov = p->ov;
+    p->w = w;
+    p->r0 = NONE;
+    p->r1 = NONE;
+    if (ov) {
+        u32 h = ov;
+        rd_clear(c, m, &h);
+        p->ov = 0;
     }
+}
+
+IGD void cell_init(AmCell* p, u32 w) {
+    p->w = w;
+    p->r0 = NONE;
+    p->r1 = NONE;
+    p->ov = 0;
+}
+
+IGD void free_edges(DevCtx& c, Shared& sh, SrcSet& s, const DAlloc& a) {
+    const AmCell* cells = am_cells(c, a);
+    for (u32 l = 0; l < a.ncells; ++l) cell_free_edges(c, sh, s, am_load(cells + l));
 }
 
 IGN void release_readers(DevCtx& c, const DAlloc& a) {
-    u32* rd = W32(c, a.rd_off);
-    for (u32 l = 0; l < a.ncells; ++l) rd_clear(c, a.mem, &rd[l]);
+    AmCell* cells = am_cells(c, a);
+    for (u32 l = 0; l < a.ncells; ++l)
+        if (cells[l].ov) rd_clear(c, a.mem, &cells[l].ov);
 }
 
 IGD void live_remove(DevCtx& c, u32 b, u32 m, u32 id) {
@@ -1200,8 +1398,7 @@ IGN void alloc_phase(DevCtx& c, Shared& sh) {
     if (tid() == 0) {
         for (u32 i = 0; i < total_allocs; ++i) {
             DAlloc& na = c.allocs[sh.s.next_alloc + i];
-            na.writer_off = heap_alloc(c, sh, na.ncells);
-            na.rd_off = heap_alloc(c, sh, na.ncells);
+            na.am_off = heap_alloc(c, sh, 4 * na.ncells);
         }
     }
     if (failed(sh)) return;
@@ -1219,39 +1416,35 @@ IGN void alloc_phase(DevCtx& c, Shared& sh) {
                 DAlloc& na = c.allocs[nid];
                 const u32 xa = x++;
                 put_instr(c, xa, IG_ALLOC, 0, sh.t_id, NONE, b, m, 0xFFFF, nid, 0, na.lo, na.hi);
-                Src s0 = worker_src(c);
+                SrcSet s0;
+                ss_init(c, s0);
                 stage(c, sh, xa, s0);
-                u32* wr = W32(c, na.writer_off);
-                u32* rd = W32(c, na.rd_off);
-                for (u32 l = 0; l < na.ncells; ++l) {
-                    wr[l] = xa;
-                    rd[l] = 0;
-                }
+                AmCell* ncl = am_cells(c, na);
+                for (u32 l = 0; l < na.ncells; ++l) cell_init(ncl + l, xa | W_ALLOC);
                 const u32 nabs = absorbed_of(c, b, m, bx + 6 * i, absorb);
                 for (u32 q = 0; q < nabs; ++q) {
                     const DAlloc& old = c.allocs[absorb[q]];
+                    AmCell* ocl = am_cells(c, old);
                     const u32 nc = utd_cells(c, sh, old, m, cells);
                     canon_cells(cells, nc, B.n[1], B.n[2], [&](u32 a0, u32 a1, u32 b0, u32 b1, u32 c0, u32 c1) {
                         const u32 xc = x++;
                         i64 lo[3] = {bps(c, B, 0)[a0], bps(c, B, 1)[b0], bps(c, B, 2)[c0]};
                         i64 hi[3] = {bps(c, B, 0)[a1], bps(c, B, 1)[b1], bps(c, B, 2)[c1]};
                         put_instr(c, xc, IG_COPY, IG_F_RESIZE, sh.t_id, NONE, b, m, m, nid, absorb[q], lo, hi);
-                        Src s = worker_src(c);
+                        SrcSet s;
+                        ss_init(c, s);
                         for (u32 i0 = a0; i0 < a1; ++i0)
                             for (u32 i1 = b0; i1 < b1; ++i1)
                                 for (u32 i2 = c0; i2 < c1; ++i2) {
-                                    edges_read(c, sh, s, old, alloc_local(old, i0, i1, i2));
-                                    edges_write(c, sh, s, na, alloc_local(na, i0, i1, i2));
+                                    cell_read_edge(sh, s, am_load(ocl + alloc_local(old, i0, i1, i2)));
+                                    cell_write_edge(c, sh, s, am_load(ncl + alloc_local(na, i0, i1, i2)));
                                 }
                         stage(c, sh, xc, s);
                         for (u32 i0 = a0; i0 < a1; ++i0)
                             for (u32 i1 = b0; i1 < b1; ++i1)
                                 for (u32 i2 = c0; i2 < c1; ++i2) {
-                                    const u32 lo_ = alloc_local(old, i0, i1, i2);
-                                    rd_append(c, sh, m, &W32(c, old.rd_off)[lo_], xc);
-                                    const u32 ln = alloc_local(na, i0, i1, i2);
-                                    wr[ln] = xc;
-                                    rd_clear(c, m, &rd[ln]);
+                                    cell_add_reader(c, sh, m, ocl + alloc_local(old, i0, i1, i2), xc);
+                                    cell_set_writer(c, m, ncl + alloc_local(na, i0, i1, i2), xc);
                                 }
                     });
                 }
@@ -1259,7 +1452,8 @@ IGN void alloc_phase(DevCtx& c, Shared& sh) {
                     DAlloc& old = c.allocs[absorb[q]];
                     const u32 xf = x++;
                     put_instr(c, xf, IG_FREE, 0, sh.t_id, NONE, b, m, 0xFFFF, absorb[q], 0, old.lo, old.hi);
-                    Src s = worker_src(c);
+                    SrcSet s;
+                        ss_init(c, s);
                     free_edges(c, sh, s, old);
                     stage(c, sh, xf, s);
                     release_readers(c, old);
@@ -1283,9 +1477,8 @@ IGN void alloc_phase(DevCtx& c, Shared& sh) {
     if (tid() == 0) {
         for (u32 i = 0; i < sh.nfree; ++i) {
             DAlloc& old = c.allocs[c.miss_bd[i]];
-            heap_release(c, old.writer_off);
-            heap_release(c, old.rd_off);
-            old.writer_off = old.rd_off = 0;
+            heap_release(c, old.am_off);
+            old.am_off = 0;
         }
         sh.s.resizes += sh.nfree;
         sh.s.next_alloc += total_allocs;
@@ -1302,6 +1495,48 @@ IGN void alloc_phase(DevCtx& c, Shared& sh) {
 // producer, source allocation); canonical boxes; the memory is marked up to
 // date at once (consumer split).
 // ===========================================================================
+// Emit the copies of one consumer from its stale cells, grouped: cells[g..h)
+// share one key (producer memory, original producer, source allocation).
+IGD u32 emit_groups(DevCtx& c, Shared& sh, const u64* key, const u32* val, u32 n, const DBuf& B, u32 k, u32 b,
+                    u32 dst, u32 m, u32 off, bool write) {
+    u32 o = off, cnt = 0;
+    for (u32 g = 0; g < n;) {
+        u32 h = g;
+        while (h < n && key[h] == key[g]) ++h;
+        const u32 pm = (u32)(key[g] >> 56);
+        const u32 src = (u32)(key[g] & 0xFFFFFF);
+        const u32 nb = canon_cells(val + g, h - g, B.n[1], B.n[2], [&](u32 a0, u32 a1, u32 b0, u32 b1, u32 c0, u32 c1) {
+            if (!write) return;
+            CopyRec& cr = c.copies[o++];
+            cr.chunk = k;
+            cr.buffer = b;
+            cr.src_alloc = src;
+            cr.dst_alloc = dst;
+            cr.src_mem = pm;
+            cr.dst_mem = m;
+            cr.clo[0] = a0;
+            cr.chi[0] = a1;
+            cr.clo[1] = b0;
+            cr.chi[1] = b1;
+            cr.clo[2] = c0;
+            cr.chi[2] = c1;
+        });
+        if (write) atomicAdd(&c.inbox_cnt[pm], nb);
+        cnt += nb;
+        g = h;
+    }
+    return cnt;
+}
+
+// ===========================================================================
+// Coherence (Sec. 3.3).  Counting pass: per memory worker, consumers in
+// (chunk, access) order; stale cells grouped by (producer memory, original
+// producer, source allocation); canonical boxes; the memory is marked up to
+// date at once (consumer split).  Up to 16 stale cells of a consumer are
+// kept sorted in registers; more go through the worker's global scratch.
+// ===========================================================================
+constexpr u32 REG_NEED = 16;
+
 IGN void coherence_count(DevCtx& c, Shared& sh) {
     const u32 A = sh.t_nacc, K = c.per_dev;
     for (u32 m = tid(); m < c.n_mem; m += nt()) {
@@ -1311,9 +1546,13 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
         u32* val = c.wk_val + (size_t)tid() * c.cap_scr;
         u64* key2 = c.wk_key2 + (size_t)tid() * c.cap_scr;
         u32* val2 = c.wk_val2 + (size_t)tid() * c.cap_scr;
+        u64* lkey = sh.wkey + (size_t)tid() * REG_NEED;
+        u32* lval = sh.wval + (size_t)tid() * REG_NEED;
         u32 total = 0, kcount = 0;
         for (u32 k = d * K; k < (d + 1) * K; ++k) {
-            const bool chunk_empty = c.chunk_lo[k] >= c.chunk_hi[k] || sh.t_lo[1] >= sh.t_hi[1] || sh.t_lo[2] >= sh.t_hi[2];
+            i64 k0, k1;
+            chunk_range(c, sh.t_lo[0], sh.t_hi[0], k, k0, k1);
+            const bool chunk_empty = k0 >= k1 || sh.t_lo[1] >= sh.t_hi[1] || sh.t_lo[2] >= sh.t_hi[2];
             if (!chunk_empty) ++kcount;
             for (u32 j = 0; j < A; ++j) {
                 const u32 idx = k * IG_MAX_ACCESS + j;
@@ -1326,7 +1565,10 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                 const u32* prod = W32(c, B.prod_off);
                 const u32* pmv = W32(c, B.pm_off);
                 u64* mask = W64(c, B.mask_off);
+                u64 rk[REG_NEED];
+                u32 rv[REG_NEED];
                 u32 n = 0;
+                bool big = false;
                 for (u32 i0 = r.clo[0]; i0 < r.chi[0]; ++i0)
                     for (u32 i1 = r.clo[1]; i1 < r.chi[1]; ++i1)
                         for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2) {
@@ -1340,58 +1582,74 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                             const u32 p = eff_w(sh, prod[cell]);
                             const u32 src = live_containing_cell(c, b, pm, i0, i1, i2);
                             if (src == 0) set_error(sh, IG_E_DEVICE);
-                            if (n >= c.cap_scr) {
-                                set_error(sh, IG_E_CAPACITY);
-                                break;
+                            u64 x = ((u64)pm << 56) | ((u64)p << 24) | (u64)(src & 0xFFFFFF);
+                            if (!big && n == REG_NEED) {
+#pragma unroll
+                                for (u32 i = 0; i < REG_NEED; ++i) {
+                                    key[i] = rk[i];
+                                    val[i] = rv[i];
+                                }
+                                big = true;
                             }
-                            key[n] = ((u64)pm << 56) | ((u64)p << 24) | (u64)(src & 0xFFFFFF);
-                            val[n] = cell;
+                            if (big) {
+                                if (n >= c.cap_scr) {
+                                    set_error(sh, IG_E_CAPACITY);
+                                    continue;
+                                }
+                                key[n] = x;
+                                val[n] = cell;
+                            } else {
+                                // sorted insertion, stable: equal keys keep cell order
+                                u32 y = cell;
+                                bool shifting = false;  // past the insertion point: shift everything
+#pragma unroll
+                                for (u32 i = 0; i < REG_NEED; ++i) {
+                                    if (i < n) {
+                                        if (shifting || rk[i] > x) {
+                                            shifting = true;
+                                            const u64 tk = rk[i];
+                                            rk[i] = x;
+                                            x = tk;
+                                            const u32 tv = rv[i];
+                                            rv[i] = y;
+                                            y = tv;
+                                        }
+                                    } else if (i == n) {
+                                        rk[i] = x;
+                                        rv[i] = y;
+                                    }
+                                }
+                            }
                             ++n;
                         }
                 if (n == 0) continue;
                 const u32 dst = live_containing(c, b, m, r.lo, r.hi);
                 if (dst == 0) set_error(sh, IG_E_DEVICE);
-                msort_kv(key, val, key2, val2, n);
-                // count, reserve, then write the copies
-                u32 cnt = 0;
-                for (u32 g = 0; g < n;) {
-                    u32 h = g;
-                    while (h < n && key[h] == key[g]) ++h;
-                    cnt += canon_cells(val + g, h - g, B.n[1], B.n[2], [](u32, u32, u32, u32, u32, u32) {});
-                    g = h;
+                const u64* gk;
+                const u32* gv;
+                if (big) {
+                    msort_kv(key, val, key2, val2, n);
+                    gk = key;
+                    gv = val;
+                } else {
+#pragma unroll
+                    for (u32 i = 0; i < REG_NEED; ++i)
+                        if (i < n) {
+                            lkey[i] = rk[i];
+                            lval[i] = rv[i];
+                        }
+                    gk = lkey;
+                    gv = lval;
                 }
+                const u32 cnt = emit_groups(c, sh, gk, gv, n, B, k, b, dst, m, 0, false);
                 const u32 off = atomicAdd(&sh.copy_top, cnt);
                 if (off + cnt > c.cap_unit) {
                     set_error(sh, IG_E_CAPACITY);
                     continue;
                 }
-                u32 o = off;
-                for (u32 g = 0; g < n;) {
-                    u32 h = g;
-                    while (h < n && key[h] == key[g]) ++h;
-                    const u32 pm = (u32)(key[g] >> 56);
-                    const u32 src = (u32)(key[g] & 0xFFFFFF);
-                    const u32 nb = canon_cells(val + g, h - g, B.n[1], B.n[2],
-                                               [&](u32 a0, u32 a1, u32 b0, u32 b1, u32 c0, u32 c1) {
-                                                   CopyRec& cr = c.copies[o++];
-                                                   cr.chunk = k;
-                                                   cr.buffer = b;
-                                                   cr.src_alloc = src;
-                                                   cr.dst_alloc = dst;
-                                                   cr.src_mem = pm;
-                                                   cr.dst_mem = m;
-                                                   cr.clo[0] = a0;
-                                                   cr.chi[0] = a1;
-                                                   cr.clo[1] = b0;
-                                                   cr.chi[1] = b1;
-                                                   cr.clo[2] = c0;
-                                                   cr.chi[2] = c1;
-                                               });
-                    atomicAdd(&c.inbox_cnt[pm], nb);
-                    g = h;
-                }
+                emit_groups(c, sh, gk, gv, n, B, k, b, dst, m, off, true);
                 // consumer split: the data is now present on m
-                for (u32 i = 0; i < n; ++i) atomicOr(&mask[(size_t)val[i] * c.mw + (m >> 6)], 1ull << (m & 63));
+                for (u32 i = 0; i < n; ++i) atomicOr(&mask[(size_t)gv[i] * c.mw + (m >> 6)], 1ull << (m & 63));
                 c.cons_off[idx] = off;
                 c.cons_cnt[idx] = cnt;
                 total += cnt;
@@ -1423,23 +1681,23 @@ IGN void coherence_emit(DevCtx& c, Shared& sh, u32 copy_first) {
                     const bool inter = cr.src_mem >= 2 && (cr.src_mem - 2) / c.devices != (m - 2) / c.devices;
                     put_instr(c, x, IG_COPY, inter ? IG_F_INTER_NODE : 0, sh.t_id, k, cr.buffer, m, cr.src_mem,
                               cr.dst_alloc, cr.src_alloc, lo, hi);
-                    Src s = worker_src(c);
+                    const AmCell* scl = am_cells(c, sa);
+                    AmCell* dcl = am_cells(c, da);
+                    SrcSet s;
+                    ss_init(c, s);
                     for (u32 i0 = cr.clo[0]; i0 < cr.chi[0]; ++i0)
                         for (u32 i1 = cr.clo[1]; i1 < cr.chi[1]; ++i1)
                             for (u32 i2 = cr.clo[2]; i2 < cr.chi[2]; ++i2) {
-                                edges_read(c, sh, s, sa, alloc_local(sa, i0, i1, i2));
-                                edges_write(c, sh, s, da, alloc_local(da, i0, i1, i2));
+                                const AmCell es = am_load(scl + alloc_local(sa, i0, i1, i2));
+                                const AmCell ed = am_load(dcl + alloc_local(da, i0, i1, i2));
+                                cell_read_edge(sh, s, es);
+                                cell_write_edge(c, sh, s, ed);
                             }
                     stage(c, sh, x, s);
-                    u32* wr = W32(c, da.writer_off);
-                    u32* rd = W32(c, da.rd_off);
                     for (u32 i0 = cr.clo[0]; i0 < cr.chi[0]; ++i0)
                         for (u32 i1 = cr.clo[1]; i1 < cr.chi[1]; ++i1)
-                            for (u32 i2 = cr.clo[2]; i2 < cr.chi[2]; ++i2) {
-                                const u32 l = alloc_local(da, i0, i1, i2);
-                                wr[l] = x;
-                                rd_clear(c, m, &rd[l]);
-                            }
+                            for (u32 i2 = cr.clo[2]; i2 < cr.chi[2]; ++i2)
+                                cell_set_writer(c, m, dcl + alloc_local(da, i0, i1, i2), x);
                     const u32 slot = atomicAdd(&c.inbox_cur[cr.src_mem], 1u);
                     InboxRec& ib = c.inbox[slot];
                     ib.alloc = cr.src_alloc;
@@ -1460,11 +1718,11 @@ IGN void inbox_drain(DevCtx& c, Shared& sh) {
         for (u32 q = lo; q < hi; ++q) {
             const InboxRec& ib = c.inbox[q];
             const DAlloc& a = c.allocs[ib.alloc];
-            u32* rd = W32(c, a.rd_off);
+            AmCell* cl = am_cells(c, a);
             for (u32 i0 = ib.clo[0]; i0 < ib.chi[0]; ++i0)
                 for (u32 i1 = ib.clo[1]; i1 < ib.chi[1]; ++i1)
                     for (u32 i2 = ib.clo[2]; i2 < ib.chi[2]; ++i2)
-                        rd_append(c, sh, m, &rd[alloc_local(a, i0, i1, i2)], ib.reader);
+                        cell_add_reader(c, sh, m, cl + alloc_local(a, i0, i1, i2), ib.reader);
         }
     }
 }
@@ -1479,8 +1737,9 @@ IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
         const u32 d = m - 2;
         u32 r = 0;
         for (u32 k = d * K; k < (d + 1) * K; ++k) {
-            const i64 lo[3] = {c.chunk_lo[k], sh.t_lo[1], sh.t_lo[2]};
-            const i64 hi[3] = {c.chunk_hi[k], sh.t_hi[1], sh.t_hi[2]};
+            i64 lo[3] = {0, sh.t_lo[1], sh.t_lo[2]};
+            i64 hi[3] = {0, sh.t_hi[1], sh.t_hi[2]};
+            chunk_range(c, sh.t_lo[0], sh.t_hi[0], k, lo[0], hi[0]);
             if (box_empty(lo, hi)) continue;
             const u32 x = kern_first + c.kdev_base[d] + r;
             const u64 bi = sh.s.n_binds + (u64)(c.kdev_base[d] + r) * A;
@@ -1495,17 +1754,19 @@ IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
                 c.b_access[bi + j] = j;
                 c.b_alloc[bi + j] = al[j];
             }
-            Src s = worker_src(c);
+            SrcSet s;
+            ss_init(c, s);
             for (u32 j = 0; j < A; ++j) {
                 if (!al[j]) continue;
                 const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
                 const DAlloc& a = c.allocs[al[j]];
+                const AmCell* cl = am_cells(c, a);
                 for (u32 i0 = rg.clo[0]; i0 < rg.chi[0]; ++i0)
                     for (u32 i1 = rg.clo[1]; i1 < rg.chi[1]; ++i1)
                         for (u32 i2 = rg.clo[2]; i2 < rg.chi[2]; ++i2) {
-                            const u32 l = alloc_local(a, i0, i1, i2);
-                            if (rg.mode & IG_READ) edges_read(c, sh, s, a, l);
-                            if (rg.mode & IG_WRITE) edges_write(c, sh, s, a, l);
+                            const AmCell e = am_load(cl + alloc_local(a, i0, i1, i2));
+                            if (rg.mode & IG_READ) cell_read_edge(sh, s, e);
+                            if (rg.mode & IG_WRITE) cell_write_edge(c, sh, s, e);
                         }
             }
             stage(c, sh, x, s);
@@ -1514,28 +1775,25 @@ IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
                 const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
                 if (!al[j] || !(rg.mode & IG_READ)) continue;
                 const DAlloc& a = c.allocs[al[j]];
-                u32* rd = W32(c, a.rd_off);
+                AmCell* cl = am_cells(c, a);
                 for (u32 i0 = rg.clo[0]; i0 < rg.chi[0]; ++i0)
                     for (u32 i1 = rg.clo[1]; i1 < rg.chi[1]; ++i1)
                         for (u32 i2 = rg.clo[2]; i2 < rg.chi[2]; ++i2)
-                            rd_append(c, sh, m, &rd[alloc_local(a, i0, i1, i2)], x);
+                            cell_add_reader(c, sh, m, cl + alloc_local(a, i0, i1, i2), x);
             }
             for (u32 j = 0; j < A; ++j) {
                 const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
                 if (!al[j] || !(rg.mode & IG_WRITE)) continue;
                 const DAlloc& a = c.allocs[al[j]];
                 const DBuf& B = c.bufs[rg.buffer];
-                u32* wr = W32(c, a.writer_off);
-                u32* rd = W32(c, a.rd_off);
+                AmCell* cl = am_cells(c, a);
                 u32* prod = W32(c, B.prod_off);
                 u32* pmv = W32(c, B.pm_off);
                 u64* mask = W64(c, B.mask_off);
                 for (u32 i0 = rg.clo[0]; i0 < rg.chi[0]; ++i0)
                     for (u32 i1 = rg.clo[1]; i1 < rg.chi[1]; ++i1)
                         for (u32 i2 = rg.clo[2]; i2 < rg.chi[2]; ++i2) {
-                            const u32 l = alloc_local(a, i0, i1, i2);
-                            wr[l] = x;
-                            rd_clear(c, m, &rd[l]);
+                            cell_set_writer(c, m, cl + alloc_local(a, i0, i1, i2), x);
                             const u32 cell = cell_of(B, i0, i1, i2);
                             prod[cell] = x;
                             pmv[cell] = m;
@@ -1579,14 +1837,19 @@ IGN void load_task(DevCtx& c, Shared& sh, u32 ci) {
 
 IGN void compile_task(DevCtx& c, Shared& sh, u32 ci, bool fresh) {
     tick(c, sh, PH_LOOKAHEAD);
+    const bool covered = fresh && sh.t_covered;
     if (!fresh) {
         load_task(c, sh, ci);
         compute_regions(c, sh);
     }
     unit_begin(c, sh);
     tick(c, sh, PH_COMPILE_REGIONS);
-    alloc_phase(c, sh);
-    if (failed(sh)) return;
+    if (!covered) {
+        alloc_phase(c, sh);
+        if (failed(sh)) return;
+    } else if (tid() == 0) {
+        sh.n_alloc_instr = 0;
+    }
     tick(c, sh, PH_ALLOC);
     for (u32 i = tid(); i < c.n_mem; i += nt()) c.inbox_cnt[i] = 0;
     bar();
@@ -1754,6 +2017,8 @@ IGN void flush_queue(DevCtx& c, Shared& sh) {
 IGN void push_command(DevCtx& c, Shared& sh, u32 entry, bool allocating) {
     const u32 qlen = uniform(sh.s.qlen);
     if (!c.lookahead || (qlen == 0 && !allocating)) {
+        // compiled at once; without lookahead an allocating task still
+        // compiles now, with its allocation phase
         if (tid() == 0) sh.win_n = 0;
         bar();
         compile_entry(c, sh, entry, !(entry & 0x80000000u));
@@ -1860,7 +2125,9 @@ IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
     }
     bar();
     tick(c, sh, PH_INTAKE_CHECKS);
-    const bool allocating = c.lookahead ? task_allocating(c, sh) : false;
+    const bool allocating = task_allocating(c, sh);
+    if (tid() == 0) sh.t_covered = (sh.s.qlen == 0 && !allocating) ? 1u : 0u;
+    bar();
     tick(c, sh, PH_LOOKAHEAD);
     push_command(c, sh, ci, allocating);
     if (failed(sh)) return;
@@ -1894,6 +2161,10 @@ IGN void create_buffer(DevCtx& c, Shared& sh, const DevCmd& cmd) {
                     WI64(c, B.bp_off[d])[0] = 0;
                     WI64(c, B.bp_off[d])[1] = cmd.ext[d];
                 }
+            }
+            for (u32 d = 0; d < 3; ++d) {
+                B.hx_off[d] = 0;
+                if (B.bp_off[d]) hx_build(c, sh, B, d);
             }
             B.ncells = 1;
             B.prod_off = heap_alloc(c, sh, 1);
@@ -1929,12 +2200,8 @@ IGN void create_buffer(DevCtx& c, Shared& sh, const DevCmd& cmd) {
                             a.clo[d] = 0;
                             a.chi[d] = 1;
                         }
-                        a.writer_off = heap_alloc(c, sh, 1);
-                        a.rd_off = heap_alloc(c, sh, 1);
-                        if (!sh.s.error) {
-                            W32(c, a.writer_off)[0] = sh.s.S;
-                            W32(c, a.rd_off)[0] = 0;
-                        }
+                        a.am_off = heap_alloc(c, sh, 4);
+                        if (!sh.s.error) cell_init(am_cells(c, a), sh.s.S);
                         c.live[(b * c.n_mem + 0) * MAX_LIVE] = id;
                         c.live_n[b * c.n_mem + 0] = 1;
                         B.user_alloc = id;
@@ -1972,7 +2239,8 @@ IGN void destroy_buffer(DevCtx& c, Shared& sh, u32 b) {
         if (owner_of(a.mem) != tid()) continue;
         const u32 x = sh.unit_first + i;
         put_instr(c, x, IG_FREE, 0, NONE, NONE, b, a.mem, 0xFFFF, c.cons_off[i], 0, a.lo, a.hi);
-        Src s = worker_src(c);
+        SrcSet s;
+                        ss_init(c, s);
         free_edges(c, sh, s, a);
         stage(c, sh, x, s);
         release_readers(c, a);
@@ -1984,8 +2252,7 @@ IGN void destroy_buffer(DevCtx& c, Shared& sh, u32 b) {
         for (u32 i = 0; i < n; ++i) {
             DAlloc& a = c.allocs[c.cons_off[i]];
             a.alive = 0;
-            heap_release(c, a.writer_off);
-            heap_release(c, a.rd_off);
+            heap_release(c, a.am_off);
         }
         for (u32 m = 0; m < c.n_mem; ++m) c.live_n[b * c.n_mem + m] = 0;
         B.alive = 0;
@@ -1999,10 +2266,12 @@ IGN void destroy_buffer(DevCtx& c, Shared& sh, u32 b) {
         if (B.user_alloc) {
             DAlloc& ua = c.allocs[B.user_alloc];
             ua.alive = 0;
-            heap_release(c, ua.writer_off);
-            heap_release(c, ua.rd_off);
+            heap_release(c, ua.am_off);
         }
-        for (u32 d = 0; d < 3; ++d) heap_release(c, B.bp_off[d]);
+        for (u32 d = 0; d < 3; ++d) {
+            heap_release(c, B.bp_off[d]);
+            heap_release(c, B.hx_off[d]);
+        }
         heap_release(c, B.prod_off);
         heap_release(c, B.pm_off);
         heap_release(c, B.mask_off);
@@ -2136,7 +2405,24 @@ using namespace igd;
 // Kernels
 // ===========================================================================
 #ifndef IG_HOST_SIM
-__global__ void __launch_bounds__(1024) ig_analyse(DevCtx* const* ctxs) {
+// The analysis kernel is compiled twice: here for workgroups of up to 256
+// threads (a register budget of up to 512 per lane, so the per-worker source
+// sets and cell records stay in registers), and in ig_kernels_wide.hip for up
+// to 1024 threads (128 registers per lane).
+#ifdef IG_WIDE_ONLY
+__global__ void __launch_bounds__(1024) ig_analyse_wide(DevCtx* const* ctxs) {
+    __shared__ Shared sh;
+    analyse(*ctxs[blockIdx.x], sh);
+}
+
+namespace igrt {
+int launch_analyse_wide(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, void* stream) {
+    hipLaunchKernelGGL(ig_analyse_wide, dim3(n_blocks), dim3(threads), 0, (hipStream_t)stream, ptrs);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+}  // namespace igrt
+#else
+__global__ void __launch_bounds__(256) ig_analyse(DevCtx* const* ctxs) {
     __shared__ Shared sh;
     analyse(*ctxs[blockIdx.x], sh);
 }
@@ -2251,6 +2537,10 @@ double clock_khz() {
     return (double)khz;
 }
 int launch_analyse(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, void* stream) {
+    if (threads > 256) {
+        if (launch_analyse_wide(ptrs, n_blocks, threads, stream) != 0) return check(hipGetLastError());
+        return 0;
+    }
     hipLaunchKernelGGL(ig_analyse, dim3(n_blocks), dim3(threads), 0, (hipStream_t)stream, ptrs);
     return check(hipGetLastError());
 }
@@ -2278,4 +2568,5 @@ int launch_stats(const DevCtx* c, uint64_t ni, uint64_t nb, uint64_t ne, DevStat
     return check(hipGetLastError());
 }
 }  // namespace igrt
-#endif
+#endif  // IG_WIDE_ONLY
+#endif  // IG_HOST_SIM
