@@ -68,12 +68,149 @@ def cpu_baseline(stream):
                       f"{dt:.2f} s"}
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def load_golden(name):
+    try:
+        with open(os.path.join(GOLDEN, name)) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
+
+
+DIGEST_KEYS = ("n_instructions", "n_bindings", "n_edges", "digest_instructions", "digest_bindings", "digest_edges")
+
+
+def run_batched(args):
+    """Config 4: 256 uneven streams, one workgroup each, one graph launch."""
+    import numpy as np
+    import torch
+    from paper_2503_10516_amd import autotune, batch, binding, streams
+
+    t = time.perf_counter()
+    ss = streams.batched()
+    log(f"batched: generated {len(ss)} streams, {sum(s.n_tasks for s in ss)} tasks ({time.perf_counter() - t:.1f} s)")
+    tuned = autotune.tune(ss, log=log) if args.batch_threads == 0 else {"threads": args.batch_threads, "window": 0}
+    threads = tuned["threads"]
+    bt = batch.Batch(ss, threads=threads)
+    t = time.perf_counter()
+    grown = bt.size(window=args.batch_window,
+                    log=lambda k, n, p: log(f"batched sizing: launch {k}, {n} streams active, "
+                                            f"{int((p[:, 2] != 0).sum())} out of capacity"))
+    log(f"batched: first analysis and sizing {time.perf_counter() - t:.1f} s, re-sized {grown}")
+    cnt = bt.counts()
+    records = int(cnt[:, 0].sum() + cnt[:, 2].sum())
+    # parity of every stream with the stored oracle results
+    gold = load_golden("batched_digests.json")
+    matched = checked = 0
+    if gold is not None:
+        rows = {r["index"]: r for r in gold["streams"]}
+        for i, ctx in enumerate(bt.contexts):
+            if i in rows:
+                st = ctx.stats()
+                checked += 1
+                matched += all(st[k] == rows[i][k] for k in DIGEST_KEYS)
+    log(f"batched: {matched}/{checked} streams equal their oracle digests")
+    bt.capture()
+    stream = torch.cuda.current_stream()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    walls = []
+    for k in range(args.batch_steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        start.record(stream)
+        bt.launch()
+        end.record(stream)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t)
+        log(f"batched: graph launch {k}: {walls[-1]:.2f} s")
+    kernel_s = start.elapsed_time(end) / 1e3
+    prog = bt.progress()
+    assert (prog[:, 2] == 0).all() and (bt.counts() == cnt).all()
+    wall = min(walls)
+    lat = np.concatenate([(lambda x: (x[:, 1] - x[:, 0]) / 1e3)(c.task_times_ns()) for c in bt.contexts])
+    # the plain single-stream path on a sample: every 16th stream by weight
+    sample = bt.order[::16]
+    t_single = 0.0
+    rec_single = 0
+    for i in sample:
+        c = bt.contexts[i]
+        c.rewind()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        c.flush()
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t
+        rec_single += int(cnt[i, 0] + cnt[i, 2])
+    single_rate = rec_single / t_single
+    heavy = bt.order[0]
+    out = {
+        "workload": f"{len(ss)} seeded streams (seed 0x{streams.BATCHED_SEED:x}): 1-3-D buffers of 2^10..2^24 "
+                    f"elements, 16..1024 chunks, 50..2000 tasks; all/slice read weights lowered to "
+                    f"{streams.BATCHED_W_ALL}/{streams.BATCHED_W_SLICE}",
+        "streams": len(ss), "tasks": int(cnt[:, 3].sum()), "instructions": int(cnt[:, 0].sum()),
+        "edges": int(cnt[:, 2].sum()), "records": records,
+        "value": records / wall, "unit": "records/s", "wall_s": wall, "kernel_s": kernel_s,
+        "graph_launches": args.batch_steps,
+        "p50_task_latency_us": float(np.percentile(lat, 50)), "p99_task_latency_us": float(np.percentile(lat, 99)),
+        "threads_per_stream": threads, "autotune": tuned, "resized": grown,
+        "oracle_digests_matched": f"{matched}/{checked}",
+        "single_stream_sample": {"streams": len(sample), "records": rec_single, "seconds": t_single,
+                                 "records_per_s": single_rate},
+        "vs_single_stream": (records / wall) / single_rate,
+        "heaviest_stream": {"name": ss[heavy].name, "records": int(cnt[heavy, 0] + cnt[heavy, 2]),
+                            "tasks": int(cnt[heavy, 3])},
+    }
+    bt.close()
+    return out
+
+
+def run_serving(args):
+    """Config 5: Poisson arrivals over sessions of the single-stream configs
+    and the growing pattern, continuous batching over 64 slots."""
+    import numpy as np
+    from paper_2503_10516_amd import serve, streams
+
+    sessions = streams.serving_sessions(n_sessions=args.serving_sessions)
+    gold = load_golden("serving_digests.json") or {}
+    server = serve.Server(slots=64, threads=args.threads)
+    rates = [float(r) for r in args.serving_rates.split(",")]
+    out = {"workload": f"{len(sessions)} sessions (seed 0x{streams.SERVING_SEED:x}) drawn from the 1-D stencil, "
+                       f"the 2-D stencil (1000 tasks), N-body (50 steps) and the growing pattern "
+                       f"(queue cap 1..64); 64 slots", "sweep": []}
+    for rate in rates:
+        r = server.run(sessions, rate, log=log)
+        matched = checked = 0
+        for s, st in zip(sessions, r.pop("session_stats")):
+            kind = s.name.split("_", 1)[1]
+            if kind in gold:
+                checked += 1
+                matched += all(st[k] == gold[kind][k] for k in DIGEST_KEYS)
+        r["oracle_digests_matched"] = f"{matched}/{checked}"
+        log(f"serving rate {rate:.0e}: p50 {r['p50_latency_us']:.0f} us, p99 {r['p99_latency_us']:.0f} us, "
+            f"{r['tasks_per_s']:.0f} tasks/s, {matched}/{checked} sessions equal their oracle digests")
+        out["sweep"].append(r)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--threads", type=int, default=256)
+    ap.add_argument("--workloads", default="stencil2d,batched,serving",
+                    help="comma list: stencil2d (the headline line), batched, serving")
+    ap.add_argument("--batch-threads", type=int, default=0, help="0: autotune")
+    ap.add_argument("--batch-window", type=int, default=400, help="commands per launch while sizing")
+    ap.add_argument("--batch-steps", type=int, default=1)
+    ap.add_argument("--serving-rates", default="1e3,1e4,1e5,1e6")
+    ap.add_argument("--serving-sessions", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (scale for the HBM counters)")
@@ -160,6 +297,14 @@ def main():
     else:
         line["cpu_baseline"] = None
     ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    work = set(args.workloads.split(","))
+    if "batched" in work:
+        line["batched"] = run_batched(args)
+        torch.cuda.empty_cache()
+    if "serving" in work:
+        line["serving"] = run_serving(args)
     print(json.dumps(line))
 
 

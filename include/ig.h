@@ -55,6 +55,20 @@ typedef int32_t ig_status;
 #define IG_E_DEVICE (-4)             /* a HIP runtime error */
 #define IG_E_BUSY (-5)               /* serving admission: no free slot */
 
+/* Which capacity an IG_E_CAPACITY raised during analysis ran out of
+ * (ig_stats.capacity_exceeded, ig_progress.capacity_exceeded). */
+#define IG_CAP_INSTRUCTIONS 1  /* cap_instructions */
+#define IG_CAP_EDGES 2         /* cap_edges */
+#define IG_CAP_BINDINGS 3      /* bindings (2 x cap_instructions) */
+#define IG_CAP_STATE 4         /* cap_state_words: cell grids and allocation maps */
+#define IG_CAP_READERS 5       /* reader-list blocks (cap_state_words / 4 blocks of 8 words) */
+#define IG_CAP_UNIT 6          /* cap_unit: instructions or staged edges of one compile unit */
+#define IG_CAP_SCRATCH 7       /* fixed per-worker scratch (boxes, grid coordinates, sources) */
+#define IG_CAP_LIVE 8          /* live or planned allocations per (memory, buffer) */
+#define IG_CAP_COMMANDS 9      /* lookahead queue (2 x cap_commands) */
+#define IG_CAP_BUFFERS 10      /* IG_MAX_BUFFERS */
+#define IG_CAP_ALLOCS 11       /* allocation ids */
+
 /* instruction kinds (Table 1: the subset on the hot path) */
 #define IG_ALLOC 1
 #define IG_COPY 2
@@ -139,6 +153,8 @@ typedef struct ig_context_desc {
     uint64_t cap_edges;         /* output edges (0: 4 * cap_instructions) */
     uint64_t cap_state_words;   /* 32-bit words for region maps and grids (0: 1<<24) */
     uint64_t cap_unit;          /* instructions of one compiled command, edges staged x8 (0: 1<<18) */
+    uint64_t cap_scratch;       /* per-worker scratch entries: grid coordinates per dimension, stale
+                                   cells of one read, sources of one instruction x2, boxes x4 (0: 8192) */
     void* arena;                /* caller-owned device memory, or NULL */
     uint64_t arena_bytes;
     void* stream;               /* hipStream_t, or NULL */
@@ -194,6 +210,9 @@ typedef struct ig_stats {
     uint64_t digest_edges;
     uint64_t commands_analysed;
     uint64_t launches;
+    uint64_t state_words_used;    /* high-water mark of the state heap (cap_state_words) */
+    uint64_t reader_blocks_used;  /* high-water mark of the reader-list blocks */
+    uint64_t capacity_exceeded;   /* IG_CAP_* after an IG_E_CAPACITY, else 0 */
     double phase_us[16];       /* device time per analysis phase (profiling builds; else 0) */
     uint64_t phase_count[16];
 } ig_stats;
@@ -245,6 +264,45 @@ ig_status ig_flush_window(ig_context* ctx);
  * per context; all must use the same `threads`).  stream: NULL = the first
  * context's stream. */
 ig_status ig_batch_flush(ig_context* const* ctxs, size_t n, void* stream);
+
+/* As ig_batch_flush, but each context analyses at most max_commands further
+ * recorded commands in this launch (0: all); later launches continue where
+ * it stopped.  Bounds the duration of one launch; the output is the same
+ * for every window. */
+ig_status ig_batch_flush_window(ig_context* const* ctxs, size_t n, void* stream, uint32_t max_commands);
+
+/* Forget the analysis results of n contexts (as ig_rewind) with one kernel
+ * launch on the stream (NULL = the first context's stream). */
+ig_status ig_batch_rewind(ig_context* const* ctxs, size_t n, void* stream);
+
+/* Progress of n contexts, gathered on the device and copied back in one
+ * transfer (waits for the stream).  tasks_done: leading tasks whose records
+ * are complete, i.e. analysed and not held in the lookahead queue;
+ * tasks_seen: tasks analysed (queued or compiled); error: a negative status
+ * raised during analysis, else 0; finished: shutdown analysed;
+ * commands_done: recorded commands analysed.  out[i] belongs to ctxs[i]. */
+typedef struct ig_progress {
+    uint64_t tasks_done;
+    uint64_t tasks_seen;
+    int32_t error;
+    uint32_t finished;
+    uint32_t capacity_exceeded;  /* IG_CAP_* after an IG_E_CAPACITY, else 0 */
+    uint32_t commands_done;      /* recorded commands analysed so far */
+} ig_progress;
+ig_status ig_batch_progress(ig_context* const* ctxs, size_t n, void* stream, ig_progress* out);
+
+/* A captured batched re-analysis (Sec. 3 graph generation for many streams
+ * in one persistent launch): the commands recorded so far are uploaded once;
+ * every ig_graph_launch forgets the previous results of all n contexts and
+ * analyses their recorded streams from the start, as ig_batch_rewind followed
+ * by ig_batch_flush would, as one HIP graph (a reset kernel, then the
+ * analysis kernel with one workgroup per context).  The graph owns a small
+ * device table of the context pointers; the contexts must outlive it and
+ * must not be re-created meanwhile.  Errors: IG_E_INVALID, IG_E_DEVICE. */
+typedef struct ig_graph ig_graph;
+ig_status ig_batch_graph_create(ig_context* const* ctxs, size_t n, void* stream, ig_graph** out);
+ig_status ig_graph_launch(ig_graph* graph, void* stream);
+ig_status ig_graph_destroy(ig_graph* graph);
 
 /* Wait for the context's outstanding work; reports IG_E_CAPACITY or
  * IG_E_DEVICE raised during analysis. */

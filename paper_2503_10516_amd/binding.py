@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 import time
-from typing import Dict, List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -57,7 +57,7 @@ class ContextDesc(ctypes.Structure):
                 ("queue_cap", ctypes.c_uint32), ("threads", ctypes.c_uint32),
                 ("cap_commands", ctypes.c_uint64), ("cap_instructions", ctypes.c_uint64),
                 ("cap_edges", ctypes.c_uint64), ("cap_state_words", ctypes.c_uint64),
-                ("cap_unit", ctypes.c_uint64),
+                ("cap_unit", ctypes.c_uint64), ("cap_scratch", ctypes.c_uint64),
                 ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_uint64),
                 ("stream", ctypes.c_void_p)]
 
@@ -70,6 +70,8 @@ class Stats(ctypes.Structure):
                 ("tasks_rejected", ctypes.c_uint64), ("digest_instructions", ctypes.c_uint64),
                 ("digest_bindings", ctypes.c_uint64), ("digest_edges", ctypes.c_uint64),
                 ("commands_analysed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("state_words_used", ctypes.c_uint64), ("reader_blocks_used", ctypes.c_uint64),
+                ("capacity_exceeded", ctypes.c_uint64),
                 ("phase_us", ctypes.c_double * 16), ("phase_count", ctypes.c_uint64 * 16)]
 
 
@@ -78,7 +80,8 @@ EXPORTS = [
     "ig_buffer_destroy", "ig_submit_task", "ig_submit_tasks", "ig_epoch", "ig_shutdown",
     "ig_flush_window", "ig_batch_flush", "ig_sync", "ig_rewind", "ig_counts",
     "ig_fetch_instructions", "ig_fetch_bindings", "ig_fetch_edges", "ig_fetch_task_status",
-    "ig_fetch_task_times", "ig_stats_get", "ig_status_str",
+    "ig_fetch_task_times", "ig_stats_get", "ig_status_str", "ig_batch_rewind", "ig_batch_progress",
+    "ig_batch_graph_create", "ig_graph_launch", "ig_graph_destroy", "ig_batch_flush_window",
 ]
 
 _libs: Dict[str, ctypes.CDLL] = {}
@@ -106,6 +109,12 @@ def lib(path: Optional[str] = None) -> ctypes.CDLL:
     for n in ("ig_epoch", "ig_shutdown", "ig_flush_window", "ig_sync", "ig_rewind"):
         getattr(L, n).argtypes = [vp]
     L.ig_batch_flush.argtypes = [P(vp), ctypes.c_size_t, vp]
+    L.ig_batch_flush_window.argtypes = [P(vp), ctypes.c_size_t, vp, ctypes.c_uint32]
+    L.ig_batch_rewind.argtypes = [P(vp), ctypes.c_size_t, vp]
+    L.ig_batch_progress.argtypes = [P(vp), ctypes.c_size_t, vp, vp]
+    L.ig_batch_graph_create.argtypes = [P(vp), ctypes.c_size_t, vp, P(vp)]
+    L.ig_graph_launch.argtypes = [vp, vp]
+    L.ig_graph_destroy.argtypes = [vp]
     L.ig_counts.argtypes = [vp] + [P(ctypes.c_uint64)] * 4
     for n in ("ig_fetch_instructions", "ig_fetch_bindings", "ig_fetch_edges", "ig_fetch_task_status"):
         getattr(L, n).argtypes = [vp, vp, ctypes.c_size_t, P(ctypes.c_size_t)]
@@ -145,30 +154,78 @@ def task_desc(task) -> TaskDesc:
     return td
 
 
-def estimate_caps(stream) -> Dict[str, int]:
-    """Generous output capacities for a stream, from its shape only: a task
-    emits at most one kernel per chunk; a read whose region is independent of
-    the chunk (all, slice, fixed) can need a copy from every chunk's producer
-    into every device, other reads a few boundary copies per chunk."""
+def project_counts(stream) -> Tuple[int, int]:
+    """A rough projection of a stream's instruction and edge counts, used only
+    to size device capacities (never for results).  It follows each buffer's
+    coherence state coarsely: an all-like read (all, fixed, slice along the
+    split dimension) of a buffer written since its last all-like read copies
+    every producer chunk's part into every other device; a neighborhood read
+    copies a few halo boxes per device; kernels depend on what they read and
+    writers on earlier readers.  Resizes are counted per task without
+    lookahead and for fixed (possibly growing) regions."""
     C = stream.chunks
-    n_dev = stream.nodes * stream.devices
-    instr = 64 + n_dev * 64 * 4
+    T = stream.nodes * stream.devices
+    K = max(1, C // T)
+    instr, edges = 1, 0
+    bufs = []
+    since_h = 0
     for c in stream.cmds:
-        if c[0] != "task":
+        if c[0] == "buffer":
+            bufs.append(dict(dirty_all=True, dirty_halo=True, host=c[4] == 1, on_dev=False, rd_all=False))
             continue
+        if c[0] != "task":
+            instr += 2 * T * max(1, len(bufs))
+            edges += 4 * T * max(1, len(bufs)) + C
+            continue
+        t = c[1]
         instr += C
-        for a in c[1].accesses:
+        edges += C * (len(t.accesses) + 1)
+        for a in t.accesses:
+            b = bufs[a.buffer]
+            if not b["on_dev"]:
+                instr += 2 * T
+                edges += 4 * T
+                b["on_dev"] = True
             if a.mode & 1:
-                instr += C * min(C, n_dev + 1) if a.mapper in (2, 3, 4) else 6 * C
-            instr += 2
-            # allocation, resize copies and free per device: every task without
-            # lookahead, tasks with fixed (possibly growing) regions with it
+                allish = a.mapper in (2, 4) or (a.mapper == 3 and a.slice_dim == 0)
+                if allish:
+                    cp = T * (C - K) + T if b["dirty_all"] else 0
+                    edges += 3 * cp + (C * (C - K) if cp else C * T)
+                    b["dirty_all"] = b["dirty_halo"] = False
+                    b["rd_all"] = True
+                elif a.mapper == 1:
+                    cp = 3 * T if b["dirty_halo"] else 0
+                    edges += 3 * cp + 3 * C
+                    b["dirty_halo"] = False
+                else:
+                    cp = T if b["host"] else 0
+                    edges += 3 * cp + C
+                b["host"] = False
+                instr += cp
+            if a.mode & 2:
+                if b["rd_all"]:
+                    edges += 2 * C * T
+                b["dirty_all"] = b["dirty_halo"] = True
+                b["rd_all"] = b["host"] = False
             if not stream.lookahead or a.mapper == 4:
-                instr += 4 * n_dev
-    instr = min(instr, 0xFFFF0000)
-    # a kernel reading a region written piecewise since the last horizon gains
-    # an edge per piece (growing read ranges), so edges get a wide margin
-    return dict(cap_commands=len(stream.cmds) + 8, cap_instructions=instr, cap_edges=10 * instr)
+                instr += 4 * T
+                edges += 8 * T + 2 * C * stream.horizon_step
+        since_h += 1
+        if since_h == stream.horizon_step:
+            since_h = 0
+            instr += 1
+            edges += C + T
+    return instr, edges
+
+
+def estimate_caps(stream, margin: float = 2.0, floor: int = 4096) -> Dict[str, int]:
+    """Output capacities for a stream: `margin` times the projected counts
+    plus a floor.  A stream that still overflows reports IG_E_CAPACITY and
+    can be re-run with larger capacities (run_stream does so)."""
+    i, e = project_counts(stream)
+    instr = min(int(margin * i) + floor, 0xFFFF0000)
+    return dict(cap_commands=len(stream.cmds) + 8, cap_instructions=instr,
+                cap_edges=int(margin * e) + 4 * floor)
 
 
 class Context:
@@ -180,14 +237,14 @@ class Context:
 
     def __init__(self, nodes, devices, chunks=0, horizon_step=0, lookahead=1, flush_horizons=0,
                  queue_cap=0, threads=0, lib_path=None, device=None, cap_commands=0,
-                 cap_instructions=0, cap_edges=0, cap_state_words=0, cap_unit=0, stream=None):
+                 cap_instructions=0, cap_edges=0, cap_state_words=0, cap_unit=0, cap_scratch=0, stream=None):
         self.L = lib(lib_path)
         d = ContextDesc()
         d.nodes, d.devices_per_node, d.chunks = nodes, devices, chunks
         d.horizon_step, d.lookahead, d.flush_horizons, d.queue_cap = horizon_step, lookahead, flush_horizons, queue_cap
         d.threads = threads
         d.cap_commands, d.cap_instructions, d.cap_edges = cap_commands, cap_instructions, cap_edges
-        d.cap_state_words, d.cap_unit = cap_state_words, cap_unit
+        d.cap_state_words, d.cap_unit, d.cap_scratch = cap_state_words, cap_unit, cap_scratch
         self.arena = None
         if device is None:
             device = "cuda" if lib_path is None else "host"
@@ -218,6 +275,30 @@ class Context:
         if st != 0:
             raise IgError("ig_buffer_create", st)
         return out.value
+
+    def submit_desc(self, td: "TaskDesc") -> None:
+        """Record a task from a descriptor built beforehand (task_desc)."""
+        st = self.L.ig_submit_task(self.h, ctypes.byref(td), None)
+        if st != 0:
+            raise IgError("ig_submit_task", st)
+
+    def record_command(self, c, td: Optional["TaskDesc"] = None) -> None:
+        """Record one stream command (td: a prebuilt descriptor of a task)."""
+        if c[0] == "task":
+            if td is not None:
+                self.submit_desc(td)
+            else:
+                self.submit(c[1])
+        elif c[0] == "buffer":
+            self.buffer_create(c[1], c[2], c[3], c[4])
+        elif c[0] == "epoch":
+            self.epoch()
+        elif c[0] == "destroy":
+            self.buffer_destroy(c[1])
+        elif c[0] == "shutdown":
+            self.shutdown()
+        else:
+            raise ValueError(c[0])
 
     def submit(self, task) -> int:
         td = task_desc(task)
@@ -333,32 +414,104 @@ class Context:
 
 def make_context(stream, lib_path=None, device=None, threads=0, **caps) -> Context:
     kw = stream.desc()
-    est = estimate_caps(stream)
+    need = ("cap_commands", "cap_instructions", "cap_edges")
+    est = {} if all(k in caps for k in need) else estimate_caps(stream)
     est.update(caps)
     return Context(lib_path=lib_path, device=device, threads=threads, **kw, **est)
 
 
 def run_stream(stream, lib_path=None, device=None, threads=0, fetch=True, **caps) -> Dict[str, object]:
-    """Record, analyse and (optionally) fetch one stream."""
-    ctx = make_context(stream, lib_path=lib_path, device=device, threads=threads, **caps)
-    ctx.record(stream)
-    t0 = time.perf_counter()
-    ctx.flush()
-    st = ctx.sync()
-    elapsed = time.perf_counter() - t0
-    if st != 0:
+    """Record, analyse and (optionally) fetch one stream.  With estimated
+    capacities, a capacity overflow is retried with larger ones (the output
+    does not depend on them); explicit capacities are used as given."""
+    margin = 2.0
+    for attempt in range(4):
+        kw = dict(caps) if caps else estimate_caps(stream, margin)
+        ctx = make_context(stream, lib_path=lib_path, device=device, threads=threads, **kw)
+        ctx.record(stream)
+        t0 = time.perf_counter()
+        ctx.flush()
+        st = ctx.sync()
+        elapsed = time.perf_counter() - t0
+        if st == IG_E_CAPACITY and not caps and attempt < 3:
+            ctx.close()
+            margin *= 3
+            continue
+        if st != 0:
+            ctx.close()
+            raise IgError("analysis", st)
+        out: Dict[str, object] = {"seconds": elapsed, "stats": ctx.stats()}
+        if fetch:
+            out.update(ctx.fetch_all())
         ctx.close()
-        raise IgError("analysis", st)
-    out: Dict[str, object] = {"seconds": elapsed, "stats": ctx.stats()}
-    if fetch:
-        out.update(ctx.fetch_all())
-    ctx.close()
-    return out
+        return out
+    raise AssertionError("unreachable")
 
 
-def batch_flush(contexts: Sequence[Context], stream=None) -> None:
-    L = contexts[0].L
-    arr = (ctypes.c_void_p * len(contexts))(*[c.h for c in contexts])
-    st = L.ig_batch_flush(arr, len(contexts), None if stream is None else stream.cuda_stream)
+class Progress(ctypes.Structure):
+    _fields_ = [("tasks_done", ctypes.c_uint64), ("tasks_seen", ctypes.c_uint64),
+                ("error", ctypes.c_int32), ("finished", ctypes.c_uint32),
+                ("capacity_exceeded", ctypes.c_uint32), ("commands_done", ctypes.c_uint32)]
+
+
+def _ctx_array(contexts):
+    return (ctypes.c_void_p * len(contexts))(*[c.h for c in contexts])
+
+
+def _stream_ptr(stream):
+    return None if stream is None else stream.cuda_stream
+
+
+def batch_rewind(contexts: Sequence[Context], stream=None) -> None:
+    st = contexts[0].L.ig_batch_rewind(_ctx_array(contexts), len(contexts), _stream_ptr(stream))
     if st != 0:
-        raise IgError("ig_batch_flush", st)
+        raise IgError("ig_batch_rewind", st)
+
+
+def batch_progress(contexts: Sequence[Context], stream=None) -> np.ndarray:
+    """(n, 6) int64: tasks_done, tasks_seen, error, finished,
+    capacity_exceeded, commands_done per context."""
+    out = (Progress * len(contexts))()
+    st = contexts[0].L.ig_batch_progress(_ctx_array(contexts), len(contexts), _stream_ptr(stream),
+                                         ctypes.cast(out, ctypes.c_void_p))
+    if st != 0:
+        raise IgError("ig_batch_progress", st)
+    return np.array([[p.tasks_done, p.tasks_seen, p.error, p.finished, p.capacity_exceeded, p.commands_done]
+                     for p in out], dtype=np.int64)
+
+
+class BatchGraph:
+    """A captured re-analysis of many contexts (reset + one batched launch)."""
+
+    def __init__(self, contexts: Sequence[Context], stream=None):
+        self.L = contexts[0].L
+        self.contexts = list(contexts)
+        self.h = ctypes.c_void_p()
+        st = self.L.ig_batch_graph_create(_ctx_array(contexts), len(contexts), _stream_ptr(stream),
+                                          ctypes.byref(self.h))
+        if st != 0:
+            raise IgError("ig_batch_graph_create", st)
+
+    def launch(self, stream=None) -> None:
+        st = self.L.ig_graph_launch(self.h, _stream_ptr(stream))
+        if st != 0:
+            raise IgError("ig_graph_launch", st)
+
+    def close(self) -> None:
+        if self.h:
+            self.L.ig_graph_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_flush(contexts: Sequence[Context], stream=None, window: int = 0) -> None:
+    """One launch over many contexts; window > 0 analyses at most that many
+    further commands per context."""
+    st = contexts[0].L.ig_batch_flush_window(_ctx_array(contexts), len(contexts), _stream_ptr(stream), window)
+    if st != 0:
+        raise IgError("ig_batch_flush_window", st)

@@ -72,13 +72,14 @@ static bool make_caps(const ig_context_desc* d, Caps& k) {
     k.cap_binds = 2 * k.cap_instr + 64;
     if (k.cap_instr >= 0xFFFFFFF0ull || k.cap_edges >= (1ull << 40)) return false;
     k.cap_heap = (u32)(d->cap_state_words ? d->cap_state_words : (1u << 24));
-    k.cap_rb = std::max<u32>(1024, k.cap_heap / 8);
+    k.cap_rb = std::max<u32>(1024, k.cap_heap / 4);
     k.cap_unit = (u32)(d->cap_unit ? d->cap_unit : (1u << 18));
     k.cap_queue = 2 * k.cap_cmds + 2;
     k.cap_allocs = 1u << 16;
-    k.cap_scr = 8192;
-    k.cap_src = 4096;
-    k.cap_box = 2048;
+    k.cap_scr = (u32)(d->cap_scratch ? d->cap_scratch : 8192);
+    if (d->cap_scratch && (d->cap_scratch < 256 || d->cap_scratch > (1u << 24))) return false;
+    k.cap_src = k.cap_scr / 2;
+    k.cap_box = k.cap_scr / 4;
     k.pack_bytes = 1ull << 24;
     return true;
 }
@@ -140,6 +141,7 @@ static u64 carve(const Caps& k, char* base, DevCtx* h, Tail* tail = nullptr) {
     TAKE(chunk_hi, i64, MAX_CHUNKS);
     TAKE(cons_off, u32, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
     TAKE(cons_cnt, u32, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
+    TAKE(cons_x, u32, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
     TAKE(copies, CopyRec, k.cap_unit);
     TAKE(dev_cnt, u32, k.n_dev);
     TAKE(dev_base, u32, k.n_dev);
@@ -164,8 +166,10 @@ static u64 carve(const Caps& k, char* base, DevCtx* h, Tail* tail = nullptr) {
     TAKE(wk_val, u32, (u64)k.n_workers * k.cap_scr);
     TAKE(wk_key2, u64, (u64)k.n_workers * k.cap_scr);
     TAKE(wk_val2, u32, (u64)k.n_workers * k.cap_scr);
-    TAKE(wk_src, u64, (u64)k.n_workers * k.cap_src);
-    TAKE(wk_src2, u64, (u64)k.n_workers * k.cap_src);
+    TAKE(wk_rsrc, u64, (u64)k.n_workers * RD_CACHE * k.cap_src);
+    TAKE(wk_grp, RdGroup, (u64)k.n_workers * RD_CACHE);
+    TAKE(wk_src, u64, (u64)k.threads * k.cap_src);  // any thread may stage a spilled source set
+    TAKE(wk_src2, u64, (u64)k.threads * k.cap_src);
     TAKE(wk_box, i64, (u64)k.n_workers * k.cap_box * 6);
 #undef TAKE
     Tail t;
@@ -449,34 +453,145 @@ ig_status ig_flush_window(ig_context* c) {
     if (!c) return IG_E_INVALID;
     const ig_status st = upload(c);
     if (st != IG_OK) return st;
-    if (igrt::launch_analyse(c->dptrs, 1, c->k.threads, c->stream) != 0) return IG_E_DEVICE;
+    if (igrt::launch_analyse(c->dptrs, 1, c->k.threads, 0, c->stream) != 0) return IG_E_DEVICE;
     c->s_valid = false;
     ++c->launches;
     return IG_OK;
 }
 
-ig_status ig_batch_flush(ig_context* const* ctxs, size_t n, void* stream) {
-    if (!ctxs || n == 0) return IG_E_INVALID;
-    const u32 threads = ctxs[0]->k.threads;
-    for (size_t i = 0; i < n; ++i) {
-        if (!ctxs[i] || ctxs[i]->k.threads != threads) return IG_E_INVALID;
-        const ig_status st = upload(ctxs[i]);
-        if (st != IG_OK) return st;
-    }
-    void* s = stream ? stream : ctxs[0]->stream;
-    // the pointer table lives in the first context's staging area
+// The device table of context pointers for a batched launch, written into
+// the first context's staging area (synchronously: the area is reused).
+static ig_status put_table(ig_context* const* ctxs, size_t n, void* s, size_t extra_bytes, DevCtx*** out) {
+    if (n * sizeof(DevCtx*) + extra_bytes > ctxs[0]->k.pack_bytes) return IG_E_CAPACITY;
     std::vector<DevCtx*> ptrs(n);
     for (size_t i = 0; i < n; ++i) ptrs[i] = ctxs[i]->dctx;
-    if (n * sizeof(DevCtx*) > ctxs[0]->k.pack_bytes) return IG_E_CAPACITY;
     DevCtx** table = (DevCtx**)ctxs[0]->pack;
+    if (igrt::stream_sync(s) != 0) return IG_E_DEVICE;
     if (igrt::copy_h2d(table, ptrs.data(), n * sizeof(DevCtx*), s) != 0) return IG_E_DEVICE;
     if (igrt::stream_sync(s) != 0) return IG_E_DEVICE;
-    if (igrt::launch_analyse(table, (unsigned)n, threads, s) != 0) return IG_E_DEVICE;
+    *out = table;
+    return IG_OK;
+}
+
+static ig_status check_batch(ig_context* const* ctxs, size_t n) {
+    if (!ctxs || n == 0 || n > 0x7FFFFFFF) return IG_E_INVALID;
+    for (size_t i = 0; i < n; ++i)
+        if (!ctxs[i] || ctxs[i]->k.threads != ctxs[0]->k.threads) return IG_E_INVALID;
+    return IG_OK;
+}
+
+static void mark_launched(ig_context* const* ctxs, size_t n, bool rewound) {
     for (size_t i = 0; i < n; ++i) {
-        ctxs[i]->s_valid = false;
-        ++ctxs[i]->launches;
+        ig_context* c = ctxs[i];
+        if (rewound) {
+            c->cur_i = c->cur_b = c->cur_e = c->cur_t = 0;
+            std::memset(&c->s, 0, sizeof c->s);
+        }
+        c->s_valid = false;
+        ++c->launches;
+    }
+}
+
+ig_status ig_batch_flush_window(ig_context* const* ctxs, size_t n, void* stream, uint32_t max_commands) {
+    ig_status st = check_batch(ctxs, n);
+    if (st != IG_OK) return st;
+    for (size_t i = 0; i < n; ++i)
+        if ((st = upload(ctxs[i])) != IG_OK) return st;
+    void* s = stream ? stream : ctxs[0]->stream;
+    DevCtx** table;
+    if ((st = put_table(ctxs, n, s, 0, &table)) != IG_OK) return st;
+    if (igrt::launch_analyse(table, (unsigned)n, ctxs[0]->k.threads, max_commands, s) != 0) return IG_E_DEVICE;
+    mark_launched(ctxs, n, false);
+    return IG_OK;
+}
+
+ig_status ig_batch_flush(ig_context* const* ctxs, size_t n, void* stream) {
+    return ig_batch_flush_window(ctxs, n, stream, 0);
+}
+
+ig_status ig_batch_rewind(ig_context* const* ctxs, size_t n, void* stream) {
+    ig_status st = check_batch(ctxs, n);
+    if (st != IG_OK) return st;
+    void* s = stream ? stream : ctxs[0]->stream;
+    DevCtx** table;
+    if ((st = put_table(ctxs, n, s, 0, &table)) != IG_OK) return st;
+    if (igrt::launch_reset(table, (unsigned)n, s) != 0) return IG_E_DEVICE;
+    for (size_t i = 0; i < n; ++i) {
+        ig_context* c = ctxs[i];
+        c->cur_i = c->cur_b = c->cur_e = c->cur_t = 0;
+        std::memset(&c->s, 0, sizeof c->s);
+        c->s_valid = false;
     }
     return IG_OK;
+}
+
+ig_status ig_batch_progress(ig_context* const* ctxs, size_t n, void* stream, ig_progress* out) {
+    if (!out) return IG_E_INVALID;
+    ig_status st = check_batch(ctxs, n);
+    if (st != IG_OK) return st;
+    void* s = stream ? stream : ctxs[0]->stream;
+    const size_t tbytes = (n * sizeof(DevCtx*) + 255) & ~(size_t)255;
+    DevCtx** table;
+    if ((st = put_table(ctxs, n, s, tbytes + 32 * n, &table)) != IG_OK) return st;
+    uint64_t* dev_out = (uint64_t*)((char*)ctxs[0]->pack + tbytes);
+    std::vector<uint64_t> host(4 * n);
+    if (igrt::launch_gather(table, (unsigned)n, dev_out, s) != 0) return IG_E_DEVICE;
+    if (igrt::copy_d2h(host.data(), dev_out, 32 * n, s) != 0) return IG_E_DEVICE;
+    if (igrt::stream_sync(s) != 0) return IG_E_DEVICE;
+    for (size_t i = 0; i < n; ++i) {
+        out[i].tasks_done = host[4 * i] & 0xFFFFFFFFu;
+        out[i].tasks_seen = host[4 * i] >> 32;
+        out[i].error = (int32_t)(uint32_t)(host[4 * i + 1] & 0xFFFFFFFFu);
+        out[i].capacity_exceeded = (uint32_t)(host[4 * i + 1] >> 32);
+        out[i].finished = (uint32_t)host[4 * i + 2];
+        out[i].commands_done = (uint32_t)host[4 * i + 3];
+    }
+    return IG_OK;
+}
+
+struct ig_graph {
+    std::vector<ig_context*> ctxs;
+    void* table = nullptr;  // device copy of the context pointers (graph-owned)
+    void* exec = nullptr;
+};
+
+ig_status ig_batch_graph_create(ig_context* const* ctxs, size_t n, void* stream, ig_graph** out) {
+    if (!out) return IG_E_INVALID;
+    ig_status st = check_batch(ctxs, n);
+    if (st != IG_OK) return st;
+    for (size_t i = 0; i < n; ++i)
+        if ((st = upload(ctxs[i])) != IG_OK) return st;
+    void* s = stream ? stream : ctxs[0]->stream;
+    ig_graph* g = new ig_graph;
+    g->ctxs.assign(ctxs, ctxs + n);
+    std::vector<DevCtx*> ptrs(n);
+    for (size_t i = 0; i < n; ++i) ptrs[i] = ctxs[i]->dctx;
+    if (igrt::dev_malloc(&g->table, n * sizeof(DevCtx*)) != 0 ||
+        igrt::copy_h2d(g->table, ptrs.data(), n * sizeof(DevCtx*), s) != 0 || igrt::stream_sync(s) != 0 ||
+        igrt::graph_capture((DevCtx* const*)g->table, (unsigned)n, ctxs[0]->k.threads, s, &g->exec) != 0) {
+        if (g->table) igrt::dev_free(g->table);
+        delete g;
+        return IG_E_DEVICE;
+    }
+    *out = g;
+    return IG_OK;
+}
+
+ig_status ig_graph_launch(ig_graph* g, void* stream) {
+    if (!g) return IG_E_INVALID;
+    void* s = stream ? stream : g->ctxs[0]->stream;
+    if (igrt::graph_launch(g->exec, s) != 0) return IG_E_DEVICE;
+    mark_launched(g->ctxs.data(), g->ctxs.size(), true);
+    return IG_OK;
+}
+
+ig_status ig_graph_destroy(ig_graph* g) {
+    if (!g) return IG_E_INVALID;
+    igrt::stream_sync(g->ctxs[0]->stream);
+    const int rc = igrt::graph_destroy(g->exec);
+    igrt::dev_free(g->table);
+    delete g;
+    return rc ? IG_E_DEVICE : IG_OK;
 }
 
 static ig_status refresh(ig_context* c) {
@@ -498,12 +613,9 @@ ig_status ig_sync(ig_context* c) {
 
 ig_status ig_rewind(ig_context* c) {
     if (!c) return IG_E_INVALID;
-    Scalars z;
-    std::memset(&z, 0, sizeof z);
-    if (igrt::memset_d(&c->dctx->s, 0, sizeof(Scalars), c->stream) != 0) return IG_E_DEVICE;
-    if (igrt::memset_d(c->h.phase, 0, 32 * sizeof(u64), c->stream) != 0) return IG_E_DEVICE;
+    if (igrt::launch_reset(c->dptrs, 1, c->stream) != 0) return IG_E_DEVICE;
     c->cur_i = c->cur_b = c->cur_e = c->cur_t = 0;
-    c->s = z;
+    std::memset(&c->s, 0, sizeof c->s);
     c->s_valid = false;
     return IG_OK;
 }
@@ -607,6 +719,9 @@ ig_status ig_stats_get(ig_context* c, ig_stats* out) {
     out->digest_edges = ds.digest[2];
     out->commands_analysed = c->s.cmd_next;
     out->launches = c->launches;
+    out->state_words_used = c->s.heap_top;
+    out->reader_blocks_used = c->s.rb_top;
+    out->capacity_exceeded = c->s.error == IG_E_CAPACITY ? c->s.cap_what : 0;
     u64 ph[32];
     if (igrt::copy_d2h(ph, c->h.phase, sizeof ph, c->stream) != 0 || igrt::stream_sync(c->stream) != 0)
         return IG_E_DEVICE;

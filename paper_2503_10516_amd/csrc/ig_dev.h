@@ -76,10 +76,22 @@ inline unsigned long long atomicCAS(unsigned long long* p, unsigned long long cm
     return cmp;
 }
 inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+inline void __threadfence_block() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 unsigned long long ig_clock();
 #define IGD inline
 #define IGN
+// bounds checks of per-thread scratch, active in the host emulation only
+#include <cstdio>
+#include <cstdlib>
+#define IG_SIM_CHECK(cond, what)                                                   \
+    do {                                                                           \
+        if (!(cond)) {                                                             \
+            std::fprintf(stderr, "ig sim: %s violated at line %d\n", what, __LINE__); \
+            std::abort();                                                          \
+        }                                                                          \
+    } while (0)
 #else
+#define IG_SIM_CHECK(cond, what) ((void)0)
 #include <hip/hip_runtime.h>
 __device__ __forceinline__ unsigned ig_tid() { return threadIdx.x; }
 __device__ __forceinline__ unsigned ig_nthreads() { return blockDim.x; }
@@ -107,6 +119,7 @@ constexpr u32 MAX_PLAN = 16;   // planned boxes per (buffer, memory) while the q
 constexpr u32 MAX_THREADS = 1024;
 constexpr u32 MAX_CHUNKS = 4096;
 constexpr u32 RB_SLOTS = 7;    // reader ids per reader block (+1 word: next)
+constexpr u32 RD_CACHE = 4;    // accesses per kernel whose read scans can be shared
 
 enum CmdKind : u32 { CMD_BUFFER = 1, CMD_TASK = 2, CMD_EPOCH = 3, CMD_DESTROY = 4, CMD_SHUTDOWN = 5 };
 
@@ -165,10 +178,16 @@ struct Region {
     u32 pad;
 };
 
+// Consecutive kernels of one device with a pure read of the same cells.
+struct RdGroup {
+    u32 alloc, first, n, nsrc;
+    u32 clo[3], chi[3];
+};
+
 // A coherence copy found in the counting pass.
 struct CopyRec {
     u32 chunk, buffer, src_alloc, dst_alloc;
-    u32 src_mem, dst_mem, pad0, pad1;
+    u32 src_mem, dst_mem, pad0, pad1;  // pad0: chunk * IG_MAX_ACCESS + access
     u32 clo[3], chi[3];
 };
 
@@ -197,6 +216,8 @@ struct Scalars {
     u32 heap_top;        // words
     u32 rb_top;          // reader blocks
     i32 error;
+    u32 done_tasks;      // leading tasks whose records are complete (none held in the queue)
+    u32 cap_what;        // with IG_E_CAPACITY: which capacity (IG_CAP_*)
     u32 pad;
 };
 
@@ -252,6 +273,7 @@ struct DevCtx {
     i64* chunk_hi;        // [MAX_CHUNKS]
     u32* cons_off;        // [MAX_CHUNKS * IG_MAX_ACCESS]
     u32* cons_cnt;        // [MAX_CHUNKS * IG_MAX_ACCESS]
+    u32* cons_x;          // [MAX_CHUNKS * IG_MAX_ACCESS] first copy of (chunk, access) within its device
     CopyRec* copies;      // [cap_unit]
     u32* dev_cnt;         // [n_dev] copies per device, then kernels per device
     u32* dev_base;        // [n_dev]
@@ -277,8 +299,10 @@ struct DevCtx {
     u32* wk_val;   // [n_workers * cap_scr]
     u64* wk_key2;  // [n_workers * cap_scr]
     u32* wk_val2;  // [n_workers * cap_scr]
-    u64* wk_src;   // [n_workers * cap_src]
-    u64* wk_src2;  // [n_workers * cap_src]
+    u64* wk_rsrc;  // [n_workers * RD_CACHE * cap_src] sources of shared read scans
+    RdGroup* wk_grp;  // [n_workers * RD_CACHE] read groups
+    u64* wk_src;   // [threads * cap_src]
+    u64* wk_src2;  // [threads * cap_src]
     i64* wk_box;   // [n_workers * cap_box * 6]
     // --- persistent scalars ---
     Scalars s;
@@ -304,8 +328,17 @@ int copy_d2h(void* dst, const void* src, size_t bytes, void* stream);
 int memset_d(void* dst, int v, size_t bytes, void* stream);
 int stream_sync(void* stream);
 double clock_khz();
-int launch_analyse(igd::DevCtx* const* dev_ctx_ptrs_device, unsigned n_blocks, unsigned threads, void* stream);
-int launch_analyse_wide(igd::DevCtx* const* dev_ctx_ptrs_device, unsigned n_blocks, unsigned threads, void* stream);
+// window: analyse at most this many further commands per context (0: all uploaded)
+int launch_analyse(igd::DevCtx* const* dev_ctx_ptrs_device, unsigned n_blocks, unsigned threads, unsigned window,
+                   void* stream);
+int launch_analyse_wide(igd::DevCtx* const* dev_ctx_ptrs_device, unsigned n_blocks, unsigned threads,
+                        unsigned window, void* stream);
+int launch_reset(igd::DevCtx* const* dev_ctx_ptrs_device, unsigned n, void* stream);
+int launch_gather(igd::DevCtx* const* dev_ctx_ptrs_device, unsigned n, uint64_t* out_dev, void* stream);
+// Capture reset + analysis of n contexts as one graph (exec: opaque handle).
+int graph_capture(igd::DevCtx* const* dev_ctx_ptrs_device, unsigned n, unsigned threads, void* stream, void** exec);
+int graph_launch(void* exec, void* stream);
+int graph_destroy(void* exec);
 int launch_pack_instructions(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_instruction* out_dev,
                              void* stream);
 int launch_pack_bindings(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_binding* out_dev, void* stream);

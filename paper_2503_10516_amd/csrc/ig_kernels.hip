@@ -38,6 +38,7 @@ struct Shared {
     u32 nfree;       // allocations freed in the allocation phase
     u32 t_dims, t_nacc, t_id, t_cmd;
     u32 t_stamps;  // some write may leave its chunk's dim-0 range: check overlaps cell by cell
+    u64 t_wbufs;   // buffers the task writes (bit per buffer)
     i64 t_lo[3], t_hi[3];
     u32 n_alloc_instr, n_new_allocs, n_copies, n_kernels;
     u32 win_first, win_n;  // lookahead window (queue positions)
@@ -54,6 +55,10 @@ IGD u32 nt() { return ig_nthreads(); }
 #define bar() ig_barrier_at(__LINE__)
 
 IGD void set_error(Shared& sh, i32 code) { atomicCAS((u32*)&sh.s.error, 0u, (u32)code); }
+// a capacity overflow, with the capacity that ran out (first one wins)
+IGD void cap_error(Shared& sh, u32 what) {
+    if (atomicCAS((u32*)&sh.s.error, 0u, (u32)IG_E_CAPACITY) == 0u) sh.s.cap_what = what;
+}
 
 // Uniform read of the error flag: every thread sees the same value because
 // nobody can set it between the two barriers.
@@ -156,7 +161,7 @@ IGD u32 heap_alloc(DevCtx& c, Shared& sh, u32 words) {
         c.heap_free[k] = c.heap[off + 2];
     } else {
         if ((u64)sh.s.heap_top + (1ull << k) > c.cap_heap) {
-            set_error(sh, IG_E_CAPACITY);
+            cap_error(sh, IG_CAP_STATE);
             return 0;
         }
         off = sh.s.heap_top;
@@ -194,8 +199,28 @@ IGD AmCell am_load(const AmCell* p) {
 
 
 // ===========================================================================
-// Reader lists: singly linked blocks of 7 ids; owned by one memory's worker.
+// Reader lists: singly linked blocks of 7 slots; owned by one memory's
+// worker.  A slot holds a reader id, or NONE, or -- with RB_RANGE set -- the
+// first id of a run of consecutive readers whose length is in the next slot
+// of the same block (the kernels of one device reading one region).
 // ===========================================================================
+constexpr u32 RB_RANGE = 0x80000000u;
+
+// f(first, count) for every reader entry of a list
+template <class F>
+IGD void rd_each(const DevCtx& c, u32 head, F f) {
+    for (u32 h = head; h; h = c.rb[h * 8 + 7])
+        for (u32 q = 0; q < RB_SLOTS; ++q) {
+            const u32 v = c.rb[h * 8 + q];
+            if (v == NONE) continue;
+            if (v & RB_RANGE) {
+                f(v & ~RB_RANGE, c.rb[h * 8 + q + 1]);
+                ++q;
+            } else {
+                f(v, 1u);
+            }
+        }
+}
 IGD u32 rb_alloc(DevCtx& c, Shared& sh, u32 m) {
     u32 h = c.rb_free[m];
     if (h) {
@@ -204,7 +229,7 @@ IGD u32 rb_alloc(DevCtx& c, Shared& sh, u32 m) {
     }
     u32 i = atomicAdd(&sh.s.rb_top, 1u);
     if (i >= c.cap_rb) {
-        set_error(sh, IG_E_CAPACITY);
+        cap_error(sh, IG_CAP_READERS);
         return 0;
     }
     return i;
@@ -229,22 +254,55 @@ IGD void rd_append(DevCtx& c, Shared& sh, u32 m, u32* head, u32 x) {
     *head = n;
 }
 
+// Return a list to its memory's free list.  Any thread may do this (the
+// whole chain is spliced in with one compare-and-swap); blocks are taken from
+// the free list only by the memory's owner, in other phases.
 IGD void rd_clear(DevCtx& c, u32 m, u32* head) {
-    u32 h = *head;
-    while (h) {
-        const u32 nx = c.rb[h * 8 + 7];
-        c.rb[h * 8 + 7] = c.rb_free[m];
-        c.rb_free[m] = h;
-        h = nx;
+    const u32 first = *head;
+    if (!first) return;
+    u32 last = first;
+    while (c.rb[last * 8 + 7]) last = c.rb[last * 8 + 7];
+    u32 old = atomicAdd(&c.rb_free[m], 0u);
+    while (true) {
+        c.rb[last * 8 + 7] = old;
+        __threadfence_block();
+        const u32 seen = atomicCAS(&c.rb_free[m], old, first);
+        if (seen == old) break;
+        old = seen;
     }
     *head = 0;
 }
 
+// a run of n >= 2 consecutive readers first..first+n-1
+IGD void rd_append_range(DevCtx& c, Shared& sh, u32 m, u32* head, u32 first, u32 n) {
+    const u32 h = *head;
+    if (h) {
+        u32* blk = c.rb + h * 8;
+        for (u32 s = 0; s + 1 < RB_SLOTS; ++s)
+            if (blk[s] == NONE && blk[s + 1] == NONE) {
+                blk[s + 1] = n;
+                blk[s] = first | RB_RANGE;
+                return;
+            }
+    }
+    const u32 b = rb_alloc(c, sh, m);
+    if (!b) return;
+    u32* blk = c.rb + b * 8;
+    blk[0] = first | RB_RANGE;
+    blk[1] = n;
+    for (u32 s = 2; s < RB_SLOTS; ++s) blk[s] = NONE;
+    blk[7] = h;
+    *head = b;
+}
+
 IGN u32 rd_copy(DevCtx& c, Shared& sh, u32 m, u32 head) {
     u32 out = 0;
-    for (u32 h = head; h; h = c.rb[h * 8 + 7])
-        for (u32 s = 0; s < RB_SLOTS; ++s)
-            if (c.rb[h * 8 + s] != NONE) rd_append(c, sh, m, &out, c.rb[h * 8 + s]);
+    rd_each(c, head, [&](u32 first, u32 n) {
+        if (n == 1)
+            rd_append(c, sh, m, &out, first);
+        else
+            rd_append_range(c, sh, m, &out, first, n);
+    });
     return out;
 }
 
@@ -346,7 +404,7 @@ IGD void src_add(Shared& sh, Src& s, u32 id, u32 kind) {
     if (s.n == s.cap) {
         s.n = src_dedup(s.buf, s.aux, s.n);
         if (s.n == s.cap) {
-            set_error(sh, IG_E_CAPACITY);
+            cap_error(sh, IG_CAP_SCRATCH);
             return;
         }
     }
@@ -361,6 +419,8 @@ struct SrcSet {
     u32 n;
     bool spilled;
     Src g;
+    // the last reader run added (cells of one region often share it)
+    u32 run_first, run_n, run_kind;
 };
 
 IGD Src worker_src(DevCtx& c);
@@ -369,10 +429,24 @@ IGD void ss_init(DevCtx& c, SrcSet& s) {
     s.n = 0;
     s.spilled = false;
     s.g = worker_src(c);
+    s.run_n = 0;
+}
+
+// a source set that spills into the given list
+IGD void ss_init_buf(SrcSet& s, u64* buf, u64* aux, u32 cap) {
+    s.n = 0;
+    s.spilled = false;
+    s.run_n = 0;
+    s.g.buf = buf;
+    s.g.aux = aux;
+    s.g.n = 0;
+    s.g.cap = cap;
 }
 
 IGD void ss_add(Shared& sh, SrcSet& s, u32 id, u32 kind) {
     if (s.spilled) {
+        // consecutive cells mostly repeat the previous source
+        if (s.g.n && s.g.buf[s.g.n - 1] == (((u64)id << 8) | kind)) return;
         src_add(sh, s.g, id, kind);
         return;
     }
@@ -412,6 +486,7 @@ IGD void ss_add(Shared& sh, SrcSet& s, u32 id, u32 kind) {
 
 IGD Src worker_src(DevCtx& c) {
     Src s;
+    IG_SIM_CHECK(tid() < c.threads, "source scratch per thread");
     s.buf = c.wk_src + (size_t)tid() * c.cap_src;
     s.aux = c.wk_src2 + (size_t)tid() * c.cap_src;
     s.n = 0;
@@ -426,7 +501,7 @@ IGN void stage_global(DevCtx& c, Shared& sh, u32 x, u64* buf, u64* aux, u32 n0) 
     const u32 n = src_dedup(buf, aux, n0);
     const u32 off = atomicAdd(&sh.stage_top, n);
     if ((u64)off + n > (u64)c.cap_unit * 8 || slot >= c.cap_unit) {
-        set_error(sh, IG_E_CAPACITY);
+        cap_error(sh, IG_CAP_UNIT);
         return;
     }
     for (u32 i = 0; i < n; ++i) {
@@ -452,7 +527,7 @@ IGD void stage(DevCtx& c, Shared& sh, u32 x, SrcSet& s) {
     const u32 n = s.n;
     const u32 off = atomicAdd(&sh.stage_top, n);
     if ((u64)off + n > (u64)c.cap_unit * 8 || slot >= c.cap_unit) {
-        set_error(sh, IG_E_CAPACITY);
+        cap_error(sh, IG_CAP_UNIT);
         return;
     }
 #pragma unroll
@@ -591,6 +666,30 @@ IGD bool box6_less(const i64* a, const i64* b) {
 }
 
 // until no two boxes merge: replace merging pairs by their bounding box
+// Append a box to a merge list, merging it into the last box when the two
+// merge.  The fixpoint of the merge rule is unique (bounding boxes only
+// grow, so any two groups that would merge in one order merge in every
+// order), which makes merging early a valid step.  Consecutive chunk boxes of
+// one device touch along dimension 0, so lists shrink by a factor of the
+// chunks per device before the quadratic fixpoint.  false: no room.
+IGD bool box_push_merge(i64* bx, u32& n, u32 cap, const i64 lo[3], const i64 hi[3]) {
+    const i64 q[6] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]};
+    if (n > 0) {
+        i64* a = bx + 6 * (n - 1);
+        if (box_merges(a, q)) {
+            for (u32 d = 0; d < 3; ++d) {
+                a[d] = a[d] < q[d] ? a[d] : q[d];
+                a[3 + d] = a[3 + d] > q[3 + d] ? a[3 + d] : q[3 + d];
+            }
+            return true;
+        }
+    }
+    if (n >= cap) return false;
+    for (u32 d = 0; d < 6; ++d) bx[6 * n + d] = q[d];
+    ++n;
+    return true;
+}
+
 IGN u32 merge_fixpoint(i64* bx, u32 n) {
     bool changed = true;
     while (changed) {
@@ -830,7 +929,7 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
             }
             newn[d] = o - 1;
             if (newn[d] > c.cap_scr) {
-                set_error(sh, IG_E_CAPACITY);
+                cap_error(sh, IG_CAP_SCRATCH);
                 break;
             }
             // old cell of each new cell
@@ -942,7 +1041,7 @@ IGN void refine_all(DevCtx& c, Shared& sh) {
     if (tid() == 0) {
         u32 n = *c.miss_n;
         if (n > c.cap_scr) {
-            set_error(sh, IG_E_CAPACITY);
+            cap_error(sh, IG_CAP_SCRATCH);
             n = 0;
         }
         u64* key = c.wk_key;
@@ -988,7 +1087,7 @@ IGN void unit_end(DevCtx& c, Shared& sh) {
     // per-instruction edge counts -> output offsets
     const u32 total = block_exscan(sh, c.tab_cnt, n);
     if ((u64)sh.s.n_edges + total > c.cap_edges) {
-        if (tid() == 0) set_error(sh, IG_E_CAPACITY);
+        if (tid() == 0) cap_error(sh, IG_CAP_EDGES);
         bar();
         return;
     }
@@ -1018,7 +1117,7 @@ IGN void unit_end(DevCtx& c, Shared& sh) {
 IGN void compile_sync(DevCtx& c, Shared& sh, bool epoch) {
     tick(c, sh, PH_OTHER);
     if ((u64)sh.s.n_instr + 1 > c.cap_instr) {
-        if (tid() == 0) set_error(sh, IG_E_CAPACITY);
+        if (tid() == 0) cap_error(sh, IG_CAP_INSTRUCTIONS);
         bar();
         return;
     }
@@ -1031,7 +1130,7 @@ IGN void compile_sync(DevCtx& c, Shared& sh, bool epoch) {
     u32 total;
     const u32 excl = block_excl(sh, cnt, &total);
     if ((u64)sh.s.n_edges + total > c.cap_edges) {
-        if (t == 0) set_error(sh, IG_E_CAPACITY);
+        if (t == 0) cap_error(sh, IG_CAP_EDGES);
         bar();
         return;
     }
@@ -1076,24 +1175,12 @@ IGN void compile_sync(DevCtx& c, Shared& sh, bool epoch) {
 // returns the number of merged boxes in the worker's box scratch, with the
 // new ones (holding an uncovered requirement of this task) first, sorted.
 IGN u32 plan_pair(DevCtx& c, Shared& sh, u32 b, u32 m, u32& n_new) {
+    IG_SIM_CHECK(tid() < c.n_workers, "box scratch per worker");
     i64* bx = c.wk_box + (size_t)tid() * c.cap_box * 6;
     u32 n = 0;
     const u32 lb = (b * c.n_mem + m) * MAX_LIVE, ln = c.live_n[b * c.n_mem + m];
     auto add = [&](const i64* lo, const i64* hi) {
-        for (u32 i = 0; i < n; ++i) {
-            const i64* q = bx + 6 * i;
-            if (q[0] == lo[0] && q[1] == lo[1] && q[2] == lo[2] && q[3] == hi[0] && q[4] == hi[1] && q[5] == hi[2])
-                return;
-        }
-        if (n >= c.cap_box) {
-            set_error(sh, IG_E_CAPACITY);
-            return;
-        }
-        i64* q = bx + 6 * n++;
-        for (u32 d = 0; d < 3; ++d) {
-            q[d] = lo[d];
-            q[3 + d] = hi[d];
-        }
+        if (!box_push_merge(bx, n, c.cap_box, lo, hi)) cap_error(sh, IG_CAP_SCRATCH);
     };
     for (u32 i = 0; i < ln; ++i) {
         const DAlloc& a = c.allocs[c.live[lb + i]];
@@ -1171,7 +1258,7 @@ IGN u32 utd_cells(DevCtx& c, Shared& sh, const DAlloc& a, u32 m, u32* out) {
                 const u32 cell = cell_of(B, i0, i1, i2);
                 if ((mask[cell * c.mw + (m >> 6)] >> (m & 63)) & 1) {
                     if (n >= c.cap_scr) {
-                        set_error(sh, IG_E_CAPACITY);
+                        cap_error(sh, IG_CAP_SCRATCH);
                         return n;
                     }
                     out[n++] = cell;
@@ -1219,6 +1306,26 @@ IGD void writer_edge(Shared& sh, SrcSet& s, const AmCell& e, u32 kind) {
         ss_add(sh, s, w, (e.w & W_ALLOC) ? IG_DEP_LIFETIME : kind);
 }
 
+// edges of kind from the readers first..first+n-1 (as eff_r maps each);
+// true if any reader still exists
+IGD bool reader_run_edges(Shared& sh, SrcSet& s, u32 first, u32 n, u32 kind) {
+    const u32 end = first + n, S = sh.s.S, E = sh.s.E;
+    u32 lo = first < E ? E : first;
+    if (lo >= end) return false;
+    if (n > 1) {
+        if (s.run_n == n && s.run_first == first && s.run_kind == kind) return true;  // added already
+        s.run_first = first;
+        s.run_n = n;
+        s.run_kind = kind;
+    }
+    if (lo < S) {
+        ss_add(sh, s, S, kind);
+        lo = S;
+    }
+    for (u32 r = lo; r < end; ++r) ss_add(sh, s, r, kind);
+    return true;
+}
+
 // a write: anti edges from the readers, else an output edge from the writer
 IGD void cell_write_edge(DevCtx& c, Shared& sh, SrcSet& s, const AmCell& e) {
     bool any = false;
@@ -1231,14 +1338,7 @@ IGD void cell_write_edge(DevCtx& c, Shared& sh, SrcSet& s, const AmCell& e) {
         ss_add(sh, s, x, IG_DEP_ANTI);
         any = true;
     }
-    for (u32 h = e.ov; h; h = c.rb[h * 8 + 7])
-        for (u32 q = 0; q < RB_SLOTS; ++q) {
-            const u32 r = c.rb[h * 8 + q];
-            if (r != NONE && eff_r(sh, r, x)) {
-                ss_add(sh, s, x, IG_DEP_ANTI);
-                any = true;
-            }
-        }
+    rd_each(c, e.ov, [&](u32 first, u32 n) { any |= reader_run_edges(sh, s, first, n, IG_DEP_ANTI); });
     if (!any) writer_edge(sh, s, e, IG_DEP_OUTPUT);
 }
 
@@ -1248,17 +1348,13 @@ IGD void cell_free_edges(DevCtx& c, Shared& sh, SrcSet& s, const AmCell& e) {
     u32 x;
     if (e.r0 != NONE && eff_r(sh, e.r0, x)) ss_add(sh, s, x, IG_DEP_LIFETIME);
     if (e.r1 != NONE && eff_r(sh, e.r1, x)) ss_add(sh, s, x, IG_DEP_LIFETIME);
-    for (u32 h = e.ov; h; h = c.rb[h * 8 + 7])
-        for (u32 q = 0; q < RB_SLOTS; ++q) {
-            const u32 r = c.rb[h * 8 + q];
-            if (r != NONE && eff_r(sh, r, x)) ss_add(sh, s, x, IG_DEP_LIFETIME);
-        }
+    rd_each(c, e.ov, [&](u32 first, u32 n) { reader_run_edges(sh, s, first, n, IG_DEP_LIFETIME); });
 }
 
 // readers gain x (inline slots first; slots whose reader reads as absent or
-// duplicates the other slot's synchronisation point are reused)
-IGD void cell_add_reader(DevCtx& c, Shared& sh, u32 m, AmCell* p, u32 x) {
-    AmCell e = am_load(p);
+// duplicates the other slot's synchronisation point are reused); e is the
+// record at p as loaded
+IGD void cell_add_reader_at(DevCtx& c, Shared& sh, u32 m, AmCell* p, AmCell e, u32 x) {
     if (e.r0 != NONE && e.r0 < sh.s.E) e.r0 = NONE;
     if (e.r1 != NONE && e.r1 < sh.s.E) e.r1 = NONE;
     if (e.r0 != NONE && e.r1 != NONE && e.r0 < sh.s.S && e.r1 < sh.s.S) e.r1 = NONE;
@@ -1273,16 +1369,51 @@ IGD void cell_add_reader(DevCtx& c, Shared& sh, u32 m, AmCell* p, u32 x) {
     }
 }
 
-// a write: new last writer, no readers
-IGD void cell_set_writer(DevCtx& c, u32 m, AmCell* p, u32 w) {
-    const u32 ov = p->ov;
-    p->w = w;
-    p->r0 = NONE;
-    p->r1 = NONE;
-    if (ov) {
-        u32 h = ov;
+IGD void cell_add_reader(DevCtx& c, Shared& sh, u32 m, AmCell* p, u32 x) {
+    cell_add_reader_at(c, sh, m, p, am_load(p), x);
+}
+
+// a write: new last writer, no readers (e: the record at p as loaded)
+IGD void cell_set_writer_at(DevCtx& c, u32 m, AmCell* p, const AmCell& e, u32 w) {
+    AmCell n;
+    n.w = w;
+    n.r0 = NONE;
+    n.r1 = NONE;
+    n.ov = 0;
+#ifdef IG_HOST_SIM
+    *p = n;
+#else
+    *(uint4*)p = make_uint4(n.w, n.r0, n.r1, n.ov);
+#endif
+    if (e.ov) {
+        u32 h = e.ov;
         rd_clear(c, m, &h);
-        p->ov = 0;
+    }
+}
+
+IGD void cell_set_writer(DevCtx& c, u32 m, AmCell* p, u32 w) { cell_set_writer_at(c, m, p, am_load(p), w); }
+
+// Visit the cells [clo, chi) (grid indices) of allocation a, loading their
+// records eight at a time so that the loads are in flight together: f(e, p)
+// gets the record as it was before the visit and its address.
+constexpr u32 CELL_BATCH = 8;
+template <class F>
+IGD void scan_cells(AmCell* cl, const DAlloc& a, const u32 clo[3], const u32 chi[3], F f) {
+    const u32 n1 = chi[1] - clo[1], n2 = chi[2] - clo[2];
+    const u32 total = (chi[0] - clo[0]) * n1 * n2;
+    for (u32 base = 0; base < total; base += CELL_BATCH) {
+        AmCell e[CELL_BATCH];
+        AmCell* ptr[CELL_BATCH];
+#pragma unroll
+        for (u32 q = 0; q < CELL_BATCH; ++q) {
+            const u32 t = base + q < total ? base + q : total - 1;
+            const u32 i2 = t % n2, i1 = (t / n2) % n1, i0 = t / (n1 * n2);
+            ptr[q] = cl + alloc_local(a, clo[0] + i0, clo[1] + i1, clo[2] + i2);
+            e[q] = am_load(ptr[q]);
+        }
+#pragma unroll
+        for (u32 q = 0; q < CELL_BATCH; ++q)
+            if (base + q < total) f(e[q], ptr[q]);
     }
 }
 
@@ -1367,8 +1498,9 @@ IGN void alloc_phase(DevCtx& c, Shared& sh) {
     const u32 total = block_exscan(sh, c.pair_cnt, NP);
     const u32 total_allocs = block_exscan(sh, c.pair_acnt, NP);
     if (tid() == 0) {
-        if (sh.unit_first + total > c.cap_instr || sh.s.next_alloc + total_allocs > c.cap_allocs || total > c.cap_unit)
-            set_error(sh, IG_E_CAPACITY);
+        if (sh.unit_first + total > c.cap_instr) cap_error(sh, IG_CAP_INSTRUCTIONS);
+        if (sh.s.next_alloc + total_allocs > c.cap_allocs) cap_error(sh, IG_CAP_ALLOCS);
+        if (total > c.cap_unit) cap_error(sh, IG_CAP_UNIT);
     }
     if (failed(sh)) return;
     // the new allocations' geometry -> thread 0 creates their map arrays
@@ -1465,7 +1597,7 @@ IGN void alloc_phase(DevCtx& c, Shared& sh) {
                 const u32 lb = (b * c.n_mem + m) * MAX_LIVE;
                 u32& ln = c.live_n[b * c.n_mem + m];
                 if (ln >= MAX_LIVE) {
-                    set_error(sh, IG_E_CAPACITY);
+                    cap_error(sh, IG_CAP_LIVE);
                 } else {
                     c.live[lb + ln] = nid;
                     ++ln;
@@ -1497,8 +1629,8 @@ IGN void alloc_phase(DevCtx& c, Shared& sh) {
 // ===========================================================================
 // Emit the copies of one consumer from its stale cells, grouped: cells[g..h)
 // share one key (producer memory, original producer, source allocation).
-IGD u32 emit_groups(DevCtx& c, Shared& sh, const u64* key, const u32* val, u32 n, const DBuf& B, u32 k, u32 b,
-                    u32 dst, u32 m, u32 off, bool write) {
+IGD u32 emit_groups(DevCtx& c, Shared& sh, const u64* key, const u32* val, u32 n, const DBuf& B, u32 k, u32 j,
+                    u32 b, u32 dst, u32 m, u32 off, bool write) {
     u32 o = off, cnt = 0;
     for (u32 g = 0; g < n;) {
         u32 h = g;
@@ -1509,6 +1641,7 @@ IGD u32 emit_groups(DevCtx& c, Shared& sh, const u64* key, const u32* val, u32 n
             if (!write) return;
             CopyRec& cr = c.copies[o++];
             cr.chunk = k;
+            cr.pad0 = k * IG_MAX_ACCESS + j;
             cr.buffer = b;
             cr.src_alloc = src;
             cr.dst_alloc = dst;
@@ -1542,6 +1675,7 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
     for (u32 m = tid(); m < c.n_mem; m += nt()) {
         if (m < 2) continue;
         const u32 d = m - 2;
+        IG_SIM_CHECK(tid() < c.n_workers, "coherence scratch per worker");
         u64* key = c.wk_key + (size_t)tid() * c.cap_scr;
         u32* val = c.wk_val + (size_t)tid() * c.cap_scr;
         u64* key2 = c.wk_key2 + (size_t)tid() * c.cap_scr;
@@ -1549,6 +1683,11 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
         u64* lkey = sh.wkey + (size_t)tid() * REG_NEED;
         u32* lval = sh.wval + (size_t)tid() * REG_NEED;
         u32 total = 0, kcount = 0;
+        // The last two read regions scanned on this memory: after a scan
+        // every cell of the region is up to date on m (or holds no data), so
+        // the same region again needs no copies.
+        u32 seen[2][7];
+        u32 n_seen = 0;
         for (u32 k = d * K; k < (d + 1) * K; ++k) {
             i64 k0, k1;
             chunk_range(c, sh.t_lo[0], sh.t_hi[0], k, k0, k1);
@@ -1561,6 +1700,22 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                 const Region& r = c.reg[idx];
                 if (chunk_empty || r.empty || !(r.mode & IG_READ)) continue;
                 const u32 b = r.buffer;
+                const u32 key7[7] = {b, r.clo[0], r.clo[1], r.clo[2], r.chi[0], r.chi[1], r.chi[2]};
+                bool again = false;
+#pragma unroll
+                for (u32 q = 0; q < 2; ++q) {
+                    bool eq = q < n_seen;
+#pragma unroll
+                    for (u32 t = 0; t < 7; ++t) eq = eq && seen[q][t] == key7[t];
+                    again = again || eq;
+                }
+                if (again) continue;
+#pragma unroll
+                for (u32 t = 0; t < 7; ++t) {
+                    seen[1][t] = seen[0][t];
+                    seen[0][t] = key7[t];
+                }
+                n_seen = n_seen < 2 ? n_seen + 1 : 2;
                 const DBuf& B = c.bufs[b];
                 const u32* prod = W32(c, B.prod_off);
                 const u32* pmv = W32(c, B.pm_off);
@@ -1593,7 +1748,7 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                             }
                             if (big) {
                                 if (n >= c.cap_scr) {
-                                    set_error(sh, IG_E_CAPACITY);
+                                    cap_error(sh, IG_CAP_SCRATCH);
                                     continue;
                                 }
                                 key[n] = x;
@@ -1641,13 +1796,13 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                     gk = lkey;
                     gv = lval;
                 }
-                const u32 cnt = emit_groups(c, sh, gk, gv, n, B, k, b, dst, m, 0, false);
+                const u32 cnt = emit_groups(c, sh, gk, gv, n, B, k, j, b, dst, m, 0, false);
                 const u32 off = atomicAdd(&sh.copy_top, cnt);
                 if (off + cnt > c.cap_unit) {
-                    set_error(sh, IG_E_CAPACITY);
+                    cap_error(sh, IG_CAP_UNIT);
                     continue;
                 }
-                emit_groups(c, sh, gk, gv, n, B, k, b, dst, m, off, true);
+                emit_groups(c, sh, gk, gv, n, B, k, j, b, dst, m, off, true);
                 // consumer split: the data is now present on m
                 for (u32 i = 0; i < n; ++i) atomicOr(&mask[(size_t)gv[i] * c.mw + (m >> 6)], 1ull << (m & 63));
                 c.cons_off[idx] = off;
@@ -1664,51 +1819,51 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
 // reads of source allocations go to their owners' inboxes.
 IGN void coherence_emit(DevCtx& c, Shared& sh, u32 copy_first) {
     const u32 A = sh.t_nacc, K = c.per_dev;
+    // instruction order: per device, (chunk, access), then canonical box
     for (u32 m = tid(); m < c.n_mem; m += nt()) {
         if (m < 2) continue;
         const u32 d = m - 2;
-        u32 x = copy_first + c.dev_base[d];
+        u32 run = 0;
         for (u32 k = d * K; k < (d + 1) * K; ++k)
             for (u32 j = 0; j < A; ++j) {
                 const u32 idx = k * IG_MAX_ACCESS + j;
-                for (u32 q = c.cons_off[idx]; q < c.cons_off[idx] + c.cons_cnt[idx]; ++q) {
-                    const CopyRec& cr = c.copies[q];
-                    const DBuf& B = c.bufs[cr.buffer];
-                    const DAlloc& sa = c.allocs[cr.src_alloc];
-                    const DAlloc& da = c.allocs[cr.dst_alloc];
-                    const i64 lo[3] = {bps(c, B, 0)[cr.clo[0]], bps(c, B, 1)[cr.clo[1]], bps(c, B, 2)[cr.clo[2]]};
-                    const i64 hi[3] = {bps(c, B, 0)[cr.chi[0]], bps(c, B, 1)[cr.chi[1]], bps(c, B, 2)[cr.chi[2]]};
-                    const bool inter = cr.src_mem >= 2 && (cr.src_mem - 2) / c.devices != (m - 2) / c.devices;
-                    put_instr(c, x, IG_COPY, inter ? IG_F_INTER_NODE : 0, sh.t_id, k, cr.buffer, m, cr.src_mem,
-                              cr.dst_alloc, cr.src_alloc, lo, hi);
-                    const AmCell* scl = am_cells(c, sa);
-                    AmCell* dcl = am_cells(c, da);
-                    SrcSet s;
-                    ss_init(c, s);
-                    for (u32 i0 = cr.clo[0]; i0 < cr.chi[0]; ++i0)
-                        for (u32 i1 = cr.clo[1]; i1 < cr.chi[1]; ++i1)
-                            for (u32 i2 = cr.clo[2]; i2 < cr.chi[2]; ++i2) {
-                                const AmCell es = am_load(scl + alloc_local(sa, i0, i1, i2));
-                                const AmCell ed = am_load(dcl + alloc_local(da, i0, i1, i2));
-                                cell_read_edge(sh, s, es);
-                                cell_write_edge(c, sh, s, ed);
-                            }
-                    stage(c, sh, x, s);
-                    for (u32 i0 = cr.clo[0]; i0 < cr.chi[0]; ++i0)
-                        for (u32 i1 = cr.clo[1]; i1 < cr.chi[1]; ++i1)
-                            for (u32 i2 = cr.clo[2]; i2 < cr.chi[2]; ++i2)
-                                cell_set_writer(c, m, dcl + alloc_local(da, i0, i1, i2), x);
-                    const u32 slot = atomicAdd(&c.inbox_cur[cr.src_mem], 1u);
-                    InboxRec& ib = c.inbox[slot];
-                    ib.alloc = cr.src_alloc;
-                    ib.reader = x;
-                    for (u32 t = 0; t < 3; ++t) {
-                        ib.clo[t] = cr.clo[t];
-                        ib.chi[t] = cr.chi[t];
-                    }
-                    ++x;
-                }
+                c.cons_x[idx] = run;
+                run += c.cons_cnt[idx];
             }
+    }
+    bar();
+    // Copies are independent: their destination cells are disjoint (each
+    // stale cell is copied once), their source cells are up to date where
+    // they are read and so are no copy's destination, and readers of the
+    // sources go to the owners' inboxes.  Any thread takes any copy.
+    const u32 n = sh.copy_top;
+    for (u32 q = tid(); q < n; q += nt()) {
+        const CopyRec& cr = c.copies[q];
+        const u32 m = cr.dst_mem, idx = cr.pad0;
+        const u32 x = copy_first + c.dev_base[m - 2] + c.cons_x[idx] + (q - c.cons_off[idx]);
+        const DBuf& B = c.bufs[cr.buffer];
+        const DAlloc& sa = c.allocs[cr.src_alloc];
+        const DAlloc& da = c.allocs[cr.dst_alloc];
+        const i64 lo[3] = {bps(c, B, 0)[cr.clo[0]], bps(c, B, 1)[cr.clo[1]], bps(c, B, 2)[cr.clo[2]]};
+        const i64 hi[3] = {bps(c, B, 0)[cr.chi[0]], bps(c, B, 1)[cr.chi[1]], bps(c, B, 2)[cr.chi[2]]};
+        const bool inter = cr.src_mem >= 2 && (cr.src_mem - 2) / c.devices != (m - 2) / c.devices;
+        put_instr(c, x, IG_COPY, inter ? IG_F_INTER_NODE : 0, sh.t_id, cr.chunk, cr.buffer, m, cr.src_mem,
+                  cr.dst_alloc, cr.src_alloc, lo, hi);
+        SrcSet s;
+        ss_init(c, s);
+        scan_cells(am_cells(c, sa), sa, cr.clo, cr.chi, [&](const AmCell& e, AmCell*) { cell_read_edge(sh, s, e); });
+        AmCell* dcl = am_cells(c, da);
+        scan_cells(dcl, da, cr.clo, cr.chi, [&](const AmCell& e, AmCell*) { cell_write_edge(c, sh, s, e); });
+        stage(c, sh, x, s);
+        scan_cells(dcl, da, cr.clo, cr.chi, [&](const AmCell& e, AmCell* p) { cell_set_writer_at(c, m, p, e, x); });
+        const u32 slot = atomicAdd(&c.inbox_cur[cr.src_mem], 1u);
+        InboxRec& ib = c.inbox[slot];
+        ib.alloc = cr.src_alloc;
+        ib.reader = x;
+        for (u32 t = 0; t < 3; ++t) {
+            ib.clo[t] = cr.clo[t];
+            ib.chi[t] = cr.chi[t];
+        }
     }
 }
 
@@ -1718,11 +1873,9 @@ IGN void inbox_drain(DevCtx& c, Shared& sh) {
         for (u32 q = lo; q < hi; ++q) {
             const InboxRec& ib = c.inbox[q];
             const DAlloc& a = c.allocs[ib.alloc];
-            AmCell* cl = am_cells(c, a);
-            for (u32 i0 = ib.clo[0]; i0 < ib.chi[0]; ++i0)
-                for (u32 i1 = ib.clo[1]; i1 < ib.chi[1]; ++i1)
-                    for (u32 i2 = ib.clo[2]; i2 < ib.chi[2]; ++i2)
-                        cell_add_reader(c, sh, m, cl + alloc_local(a, i0, i1, i2), ib.reader);
+            const u32 x = ib.reader;
+            scan_cells(am_cells(c, a), a, ib.clo, ib.chi,
+                       [&](const AmCell& e, AmCell* p) { cell_add_reader_at(c, sh, m, p, e, x); });
         }
     }
 }
@@ -1730,11 +1883,36 @@ IGN void inbox_drain(DevCtx& c, Shared& sh) {
 // ===========================================================================
 // Device kernels, bindings, buffer-map update (Sec. 3.1, 3.2)
 // ===========================================================================
+// Pure reads of a buffer the task does not write see the same writers in
+// every kernel of the task (kernels change only the cells they write), so
+// consecutive kernels of one device reading the same region share one scan
+// of its cells, and their reader entries go in as one run of ids, added
+// after the device's last kernel (nothing in between looks at them).
+IGD bool same_cells(const RdGroup& g, u32 alloc, const Region& rg) {
+    return g.alloc == alloc && g.clo[0] == rg.clo[0] && g.clo[1] == rg.clo[1] && g.clo[2] == rg.clo[2] &&
+           g.chi[0] == rg.chi[0] && g.chi[1] == rg.chi[1] && g.chi[2] == rg.chi[2];
+}
+
+IGD void rd_group_flush(DevCtx& c, Shared& sh, u32 m, RdGroup& g) {
+    const DAlloc& a = c.allocs[g.alloc];
+    const u32 first = g.first, n = g.n;
+    scan_cells(am_cells(c, a), a, g.clo, g.chi, [&](const AmCell& e, AmCell* p) {
+        if (n == 1)
+            cell_add_reader_at(c, sh, m, p, e, first);
+        else
+            rd_append_range(c, sh, m, &p->ov, first, n);
+    });
+    g.n = 0;
+}
+
 IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
     const u32 A = sh.t_nacc, K = c.per_dev;
     for (u32 m = tid(); m < c.n_mem; m += nt()) {
         if (m < 2) continue;
         const u32 d = m - 2;
+        IG_SIM_CHECK(tid() < c.n_workers, "read-group scratch per worker");
+        RdGroup* grp = c.wk_grp + (size_t)tid() * RD_CACHE;
+        for (u32 q = 0; q < RD_CACHE; ++q) grp[q].n = 0;
         u32 r = 0;
         for (u32 k = d * K; k < (d + 1) * K; ++k) {
             i64 lo[3] = {0, sh.t_lo[1], sh.t_lo[2]};
@@ -1756,44 +1934,74 @@ IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
             }
             SrcSet s;
             ss_init(c, s);
+            u32 grouped = 0;  // accesses handled by a read group
             for (u32 j = 0; j < A; ++j) {
                 if (!al[j]) continue;
                 const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
                 const DAlloc& a = c.allocs[al[j]];
-                const AmCell* cl = am_cells(c, a);
-                for (u32 i0 = rg.clo[0]; i0 < rg.chi[0]; ++i0)
-                    for (u32 i1 = rg.clo[1]; i1 < rg.chi[1]; ++i1)
-                        for (u32 i2 = rg.clo[2]; i2 < rg.chi[2]; ++i2) {
-                            const AmCell e = am_load(cl + alloc_local(a, i0, i1, i2));
-                            if (rg.mode & IG_READ) cell_read_edge(sh, s, e);
-                            if (rg.mode & IG_WRITE) cell_write_edge(c, sh, s, e);
-                        }
+                const u32 mode = rg.mode;
+                if (j < RD_CACHE && mode == IG_READ && !((sh.t_wbufs >> rg.buffer) & 1)) {
+                    grouped |= 1u << j;
+                    RdGroup& g = grp[j];
+                    u64* src = c.wk_rsrc + ((size_t)tid() * RD_CACHE + j) * c.cap_src;
+                    if (g.n && g.first + g.n == x && same_cells(g, al[j], rg)) {
+                        for (u32 i = 0; i < g.nsrc; ++i) ss_add(sh, s, (u32)(src[i] >> 8), (u32)(src[i] & 0xFF));
+                        ++g.n;
+                        continue;
+                    }
+                    if (g.n) rd_group_flush(c, sh, m, g);
+                    // the sources of this read alone, kept for the next kernels
+                    SrcSet t;
+                    ss_init_buf(t, src, c.wk_src2 + (size_t)tid() * c.cap_src, c.cap_src);
+                    scan_cells(am_cells(c, a), a, rg.clo, rg.chi,
+                               [&](const AmCell& e, AmCell*) { cell_read_edge(sh, t, e); });
+                    u32 ns;
+                    if (!t.spilled) {
+#pragma unroll
+                        for (u32 i = 0; i < REG_SRC; ++i)
+                            if (i < t.n) src[i] = t.r[i];
+                        ns = t.n;
+                    } else {
+                        ns = src_dedup(src, t.g.aux, t.g.n);
+                    }
+                    for (u32 i = 0; i < ns; ++i) ss_add(sh, s, (u32)(src[i] >> 8), (u32)(src[i] & 0xFF));
+                    g.alloc = al[j];
+                    g.first = x;
+                    g.n = 1;
+                    g.nsrc = ns;
+                    for (u32 t3 = 0; t3 < 3; ++t3) {
+                        g.clo[t3] = rg.clo[t3];
+                        g.chi[t3] = rg.chi[t3];
+                    }
+                    continue;
+                }
+                scan_cells(am_cells(c, a), a, rg.clo, rg.chi, [&](const AmCell& e, AmCell*) {
+                    if (mode & IG_READ) cell_read_edge(sh, s, e);
+                    if (mode & IG_WRITE) cell_write_edge(c, sh, s, e);
+                });
             }
             stage(c, sh, x, s);
             // reads first, then writes (a cell both read and written ends written)
             for (u32 j = 0; j < A; ++j) {
                 const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
-                if (!al[j] || !(rg.mode & IG_READ)) continue;
+                if (!al[j] || !(rg.mode & IG_READ) || ((grouped >> j) & 1)) continue;
                 const DAlloc& a = c.allocs[al[j]];
-                AmCell* cl = am_cells(c, a);
-                for (u32 i0 = rg.clo[0]; i0 < rg.chi[0]; ++i0)
-                    for (u32 i1 = rg.clo[1]; i1 < rg.chi[1]; ++i1)
-                        for (u32 i2 = rg.clo[2]; i2 < rg.chi[2]; ++i2)
-                            cell_add_reader(c, sh, m, cl + alloc_local(a, i0, i1, i2), x);
+                scan_cells(am_cells(c, a), a, rg.clo, rg.chi,
+                           [&](const AmCell& e, AmCell* p) { cell_add_reader_at(c, sh, m, p, e, x); });
             }
             for (u32 j = 0; j < A; ++j) {
                 const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
                 if (!al[j] || !(rg.mode & IG_WRITE)) continue;
                 const DAlloc& a = c.allocs[al[j]];
                 const DBuf& B = c.bufs[rg.buffer];
-                AmCell* cl = am_cells(c, a);
                 u32* prod = W32(c, B.prod_off);
                 u32* pmv = W32(c, B.pm_off);
                 u64* mask = W64(c, B.mask_off);
+                scan_cells(am_cells(c, a), a, rg.clo, rg.chi,
+                           [&](const AmCell& e, AmCell* p) { cell_set_writer_at(c, m, p, e, x); });
                 for (u32 i0 = rg.clo[0]; i0 < rg.chi[0]; ++i0)
                     for (u32 i1 = rg.clo[1]; i1 < rg.chi[1]; ++i1)
                         for (u32 i2 = rg.clo[2]; i2 < rg.chi[2]; ++i2) {
-                            cell_set_writer(c, m, cl + alloc_local(a, i0, i1, i2), x);
                             const u32 cell = cell_of(B, i0, i1, i2);
                             prod[cell] = x;
                             pmv[cell] = m;
@@ -1802,6 +2010,8 @@ IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
                         }
             }
         }
+        for (u32 q = 0; q < RD_CACHE; ++q)
+            if (grp[q].n) rd_group_flush(c, sh, m, grp[q]);
     }
 }
 
@@ -1823,24 +2033,43 @@ IGN void load_task(DevCtx& c, Shared& sh, u32 ci) {
         // dim-0 radius stay inside their chunk's dim-0 range; chunks partition
         // that range, so such writes of different chunks cannot overlap.
         u32 stamps = 0;
+        u64 wb = 0;
         for (u32 j = 0; j < cmd.task.n_access; ++j) {
             const ig_access& a = cmd.task.access[j];
             if (!(a.mode & IG_WRITE)) continue;
+            wb |= 1ull << a.buffer;
             const bool confined = a.mapper == IG_MAP_ONE_TO_ONE || (a.mapper == IG_MAP_SLICE && a.slice_dim != 0) ||
                                   (a.mapper == IG_MAP_NEIGHBORHOOD && a.radius[0] == 0);
             if (!confined) stamps = 1;
         }
         sh.t_stamps = stamps;
+        sh.t_wbufs = wb;
     }
     bar();
 }
 
+// Every requirement of the task (regions in c.reg) lies in one live
+// allocation of its memory: then the allocation phase has nothing to emit.
+IGN bool regions_covered(DevCtx& c, Shared& sh) {
+    const u32 A = sh.t_nacc, C = c.chunks;
+    if (tid() == 0) sh.flag = 0;
+    bar();
+    for (u32 idx = tid(); idx < C * A; idx += nt()) {
+        const u32 k = idx / A, j = idx % A;
+        const Region& r = c.reg[k * IG_MAX_ACCESS + j];
+        if (!r.empty && live_containing(c, r.buffer, mem_of_chunk(c, k), r.lo, r.hi) == 0) sh.flag = 1;
+    }
+    bar();
+    return sh.flag == 0;
+}
+
 IGN void compile_task(DevCtx& c, Shared& sh, u32 ci, bool fresh) {
     tick(c, sh, PH_LOOKAHEAD);
-    const bool covered = fresh && sh.t_covered;
+    bool covered = fresh && sh.t_covered;
     if (!fresh) {
         load_task(c, sh, ci);
         compute_regions(c, sh);
+        covered = regions_covered(c, sh);
     }
     unit_begin(c, sh);
     tick(c, sh, PH_COMPILE_REGIONS);
@@ -1869,9 +2098,9 @@ IGN void compile_task(DevCtx& c, Shared& sh, u32 ci, bool fresh) {
     for (u32 i = tid(); i < c.n_mem; i += nt()) c.inbox_cur[i] = c.inbox_off[i];
     const u32 n_task = sh.unit_n + n_copies + n_kernels;
     if (tid() == 0) {
-        if ((u64)sh.unit_first + n_task > c.cap_instr || n_task > c.cap_unit ||
-            sh.s.n_binds + (u64)n_kernels * sh.t_nacc > c.cap_binds)
-            set_error(sh, IG_E_CAPACITY);
+        if ((u64)sh.unit_first + n_task > c.cap_instr) cap_error(sh, IG_CAP_INSTRUCTIONS);
+        if (n_task > c.cap_unit) cap_error(sh, IG_CAP_UNIT);
+        if (sh.s.n_binds + (u64)n_kernels * sh.t_nacc > c.cap_binds) cap_error(sh, IG_CAP_BINDINGS);
     }
     if (failed(sh)) return;
     const u32 copy_first = sh.unit_first + sh.unit_n;
@@ -1961,19 +2190,14 @@ IGN void plan_merge(DevCtx& c, Shared& sh) {
                 for (u32 j = 0; j < A; ++j) {
                     const Region& r = c.reg[k * IG_MAX_ACCESS + j];
                     if (r.empty || r.buffer != b) continue;
-                    if (n >= c.cap_box) {
-                        set_error(sh, IG_E_CAPACITY);
+                    if (!box_push_merge(bx, n, c.cap_box, r.lo, r.hi)) {
+                        cap_error(sh, IG_CAP_SCRATCH);
                         break;
                     }
-                    for (u32 t = 0; t < 3; ++t) {
-                        bx[6 * n + t] = r.lo[t];
-                        bx[6 * n + 3 + t] = r.hi[t];
-                    }
-                    ++n;
                 }
             n = merge_fixpoint(bx, n);
             if (n > MAX_PLAN) {
-                set_error(sh, IG_E_CAPACITY);
+                cap_error(sh, IG_CAP_LIVE);
                 continue;
             }
             i64* p = c.plan + (size_t)pi * MAX_PLAN * 6;
@@ -2027,7 +2251,7 @@ IGN void push_command(DevCtx& c, Shared& sh, u32 entry, bool allocating) {
     if (allocating) plan_merge(c, sh);
     if (tid() == 0) {
         if (sh.s.qlen >= c.cap_queue) {
-            set_error(sh, IG_E_CAPACITY);
+            cap_error(sh, IG_CAP_COMMANDS);
         } else {
             c.queue[sh.s.qlen++] = entry;
             if (allocating)
@@ -2146,7 +2370,7 @@ IGN void create_buffer(DevCtx& c, Shared& sh, const DevCmd& cmd) {
     if (tid() == 0) {
         const u32 b = sh.s.n_buffers;
         if (b >= MAX_BUF) {
-            set_error(sh, IG_E_CAPACITY);
+            cap_error(sh, IG_CAP_BUFFERS);
         } else {
             DBuf& B = c.bufs[b];
             B.alive = 1;
@@ -2187,7 +2411,7 @@ IGN void create_buffer(DevCtx& c, Shared& sh, const DevCmd& cmd) {
                     // host data lives in user memory M0, produced before the current sync point
                     const u32 id = sh.s.next_alloc++;
                     if (id >= c.cap_allocs) {
-                        set_error(sh, IG_E_CAPACITY);
+                        cap_error(sh, IG_CAP_ALLOCS);
                     } else {
                         DAlloc& a = c.allocs[id];
                         a.buffer = b;
@@ -2229,7 +2453,8 @@ IGN void destroy_buffer(DevCtx& c, Shared& sh, u32 b) {
                 c.cons_off[j] = c.cons_off[j - 1];
                 c.cons_off[j - 1] = v;
             }
-        if ((u64)sh.unit_first + n > c.cap_instr || n > c.cap_unit) set_error(sh, IG_E_CAPACITY);
+        if ((u64)sh.unit_first + n > c.cap_instr) cap_error(sh, IG_CAP_INSTRUCTIONS);
+        if (n > c.cap_unit) cap_error(sh, IG_CAP_UNIT);
         sh.unit_n = n;
     }
     if (failed(sh)) return;
@@ -2312,16 +2537,30 @@ IGN void init_state(DevCtx& c, Shared& sh) {
     bar();
 }
 
-IGN void analyse(DevCtx& c, Shared& sh) {
+// Tasks are compiled in id order; those before the first task still held in
+// the lookahead queue have all their records.
+IGD u32 done_prefix(const DevCtx& c, const Scalars& s) {
+    for (u32 i = 0; i < s.qlen; ++i) {
+        const u32 e = c.queue[i];
+        if (!(e & 0x80000000u)) return c.cmds[e].arg;
+    }
+    return s.n_tasks;
+}
+
+// Analyse the uploaded commands from the context's position on; window > 0
+// stops after that many commands (the rest follows in later launches).
+IGN void analyse(DevCtx& c, Shared& sh, u32 window) {
     if (tid() == 0) {
         sh.s = c.s;
         sh.tick = ig_clock();
     }
     bar();
+    const u32 first = sh.s.cmd_next;
+    const u32 end = window && c.cmd_end - first > window ? first + window : c.cmd_end;
     if (uniform(sh.s.cmd_next == 0 && sh.s.n_instr == 0)) init_state(c, sh);
     while (true) {
         const u32 ci = sh.s.cmd_next;
-        const bool go = ci < c.cmd_end && sh.s.error == 0;
+        const bool go = ci < end && sh.s.error == 0;
         bar();
         if (!go) break;
         const DevCmd& cmd = c.cmds[ci];
@@ -2361,7 +2600,25 @@ IGN void analyse(DevCtx& c, Shared& sh) {
         bar();
     }
     bar();
-    if (tid() == 0) c.s = sh.s;
+    if (tid() == 0) {
+        sh.s.done_tasks = done_prefix(c, sh.s);
+        c.s = sh.s;
+    }
+}
+
+// Forget all analysis results of one context (block-wide).
+IGD void reset_state(DevCtx& c, u32 t, u32 n) {
+    u32* w = (u32*)&c.s;
+    for (u32 i = t; i < sizeof(Scalars) / 4; i += n) w[i] = 0;
+    for (u32 i = t; i < 32; i += n) c.phase[i] = 0;
+}
+
+// Progress of one context: done tasks, seen tasks, error, finished.
+IGD void gather_progress(const DevCtx& c, u64* out) {
+    out[0] = c.s.done_tasks | ((u64)c.s.n_tasks << 32);
+    out[1] = (u64)(u32)c.s.error | ((u64)c.s.cap_what << 32);
+    out[2] = c.s.finished;
+    out[3] = c.s.cmd_next;
 }
 
 // ===========================================================================
@@ -2410,21 +2667,30 @@ using namespace igd;
 // sets and cell records stay in registers), and in ig_kernels_wide.hip for up
 // to 1024 threads (128 registers per lane).
 #ifdef IG_WIDE_ONLY
-__global__ void __launch_bounds__(1024) ig_analyse_wide(DevCtx* const* ctxs) {
+__global__ void __launch_bounds__(1024) ig_analyse_wide(DevCtx* const* ctxs, u32 window) {
     __shared__ Shared sh;
-    analyse(*ctxs[blockIdx.x], sh);
+    analyse(*ctxs[blockIdx.x], sh, window);
 }
 
 namespace igrt {
-int launch_analyse_wide(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, void* stream) {
-    hipLaunchKernelGGL(ig_analyse_wide, dim3(n_blocks), dim3(threads), 0, (hipStream_t)stream, ptrs);
+int launch_analyse_wide(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, unsigned window, void* stream) {
+    hipLaunchKernelGGL(ig_analyse_wide, dim3(n_blocks), dim3(threads), 0, (hipStream_t)stream, ptrs, window);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 }  // namespace igrt
 #else
-__global__ void __launch_bounds__(256) ig_analyse(DevCtx* const* ctxs) {
+__global__ void __launch_bounds__(256) ig_analyse(DevCtx* const* ctxs, u32 window) {
     __shared__ Shared sh;
-    analyse(*ctxs[blockIdx.x], sh);
+    analyse(*ctxs[blockIdx.x], sh, window);
+}
+
+__global__ void __launch_bounds__(64) ig_reset(DevCtx* const* ctxs) {
+    reset_state(*ctxs[blockIdx.x], threadIdx.x, blockDim.x);
+}
+
+__global__ void __launch_bounds__(256) ig_gather(DevCtx* const* ctxs, u32 n, u64* out) {
+    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) gather_progress(*ctxs[i], out + 4 * (size_t)i);
 }
 
 __global__ void ig_pack_instructions(const DevCtx* c, u64 first, u64 n, ig_instruction* out) {
@@ -2536,15 +2802,50 @@ double clock_khz() {
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
     return (double)khz;
 }
-int launch_analyse(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, void* stream) {
+int launch_analyse(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, unsigned window, void* stream) {
     if (threads > 256) {
-        if (launch_analyse_wide(ptrs, n_blocks, threads, stream) != 0) return check(hipGetLastError());
+        if (launch_analyse_wide(ptrs, n_blocks, threads, window, stream) != 0) return check(hipGetLastError());
         return 0;
     }
-    hipLaunchKernelGGL(ig_analyse, dim3(n_blocks), dim3(threads), 0, (hipStream_t)stream, ptrs);
+    hipLaunchKernelGGL(ig_analyse, dim3(n_blocks), dim3(threads), 0, (hipStream_t)stream, ptrs, window);
     return check(hipGetLastError());
 }
 static unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+int launch_reset(DevCtx* const* ptrs, unsigned n, void* stream) {
+    if (!n) return 0;
+    hipLaunchKernelGGL(ig_reset, dim3(n), dim3(64), 0, (hipStream_t)stream, ptrs);
+    return check(hipGetLastError());
+}
+int launch_gather(DevCtx* const* ptrs, unsigned n, uint64_t* out, void* stream) {
+    if (!n) return 0;
+    hipLaunchKernelGGL(ig_gather, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, ptrs, n,
+                       (u64*)out);
+    return check(hipGetLastError());
+}
+// The graph is captured on a stream of its own (default priority) and
+// launched on the caller's stream.
+int graph_capture(DevCtx* const* ptrs, unsigned n, unsigned threads, void* stream, void** exec) {
+    (void)stream;
+    hipStream_t cs;
+    if (check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking))) return -1;
+    hipGraph_t g = nullptr;
+    int rc = check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    if (!rc) rc = launch_reset(ptrs, n, cs);
+    if (!rc) rc = launch_analyse(ptrs, n, threads, 0, cs);
+    const int rc_end = check(hipStreamEndCapture(cs, &g));
+    if (!rc) rc = rc_end;
+    hipGraphExec_t e = nullptr;
+    if (!rc) rc = check(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (rc) return rc;
+    *exec = (void*)e;
+    return 0;
+}
+int graph_launch(void* exec, void* stream) {
+    return check(hipGraphLaunch((hipGraphExec_t)exec, (hipStream_t)stream));
+}
+int graph_destroy(void* exec) { return check(hipGraphExecDestroy((hipGraphExec_t)exec)); }
 int launch_pack_instructions(const DevCtx* c, uint64_t first, uint64_t n, ig_instruction* out, void* stream) {
     if (!n) return 0;
     hipLaunchKernelGGL(ig_pack_instructions, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, c, first, n, out);

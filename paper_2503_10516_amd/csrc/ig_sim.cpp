@@ -81,7 +81,7 @@ int memset_d(void* dst, int v, size_t bytes, void*) {
 int stream_sync(void*) { return 0; }
 double clock_khz() { return 1e6; }
 
-int launch_analyse(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, void*) {
+int launch_analyse(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, unsigned window, void*) {
     for (unsigned b = 0; b < n_blocks; ++b) {
         Shared* sh = new Shared();
         igsim::Barrier gate;
@@ -94,11 +94,41 @@ int launch_analyse(DevCtx* const* ptrs, unsigned n_blocks, unsigned threads, voi
                 igsim::cur.nthreads = threads;
                 igsim::cur.block = b;
                 igsim::cur.bar = &gate;
-                analyse(*ptrs[b], *sh);
+                analyse(*ptrs[b], *sh, window);
             });
         for (auto& t : ts) t.join();
         delete sh;
     }
+    return 0;
+}
+
+int launch_reset(DevCtx* const* ptrs, unsigned n, void*) {
+    for (unsigned b = 0; b < n; ++b) reset_state(*ptrs[b], 0, 1);
+    return 0;
+}
+int launch_gather(DevCtx* const* ptrs, unsigned n, uint64_t* out, void*) {
+    for (unsigned i = 0; i < n; ++i) gather_progress(*ptrs[i], (u64*)out + 4 * (size_t)i);
+    return 0;
+}
+// A "graph" of the emulation: the recorded launch sequence, replayed.
+struct SimGraph {
+    std::vector<DevCtx*> ptrs;
+    unsigned threads;
+};
+int graph_capture(DevCtx* const* ptrs, unsigned n, unsigned threads, void*, void** exec) {
+    SimGraph* g = new SimGraph;
+    g->ptrs.assign(ptrs, ptrs + n);
+    g->threads = threads;
+    *exec = g;
+    return 0;
+}
+int graph_launch(void* exec, void* stream) {
+    SimGraph* g = (SimGraph*)exec;
+    launch_reset(g->ptrs.data(), (unsigned)g->ptrs.size(), stream);
+    return launch_analyse(g->ptrs.data(), (unsigned)g->ptrs.size(), g->threads, 0, stream);
+}
+int graph_destroy(void* exec) {
+    delete (SimGraph*)exec;
     return 0;
 }
 

@@ -256,9 +256,18 @@ def batched_stream(master_seed: int, index: int, max_tasks: int = 2000,
 
 BATCHED_SEED = 0x2503105160000004
 SERVING_SEED = 0x2503105160000005
+# Weights of the all and slice read mappers in the batched workload.  The
+# workload is defined with 0.1 each; at that mix the 256 streams project to
+# about 1.5e10 records (an all-read over 1024 chunks on 128 devices alone
+# emits ~1.3e5 copies and ~1e6 edges), so both are lowered once, to 0.005,
+# which projects to ~1.6e9 records.
+BATCHED_W_ALL = 0.005
+BATCHED_W_SLICE = 0.005
 
 
 def batched(n_streams: int = 256, **kw) -> List[Stream]:
+    kw.setdefault("w_all", BATCHED_W_ALL)
+    kw.setdefault("w_slice", BATCHED_W_SLICE)
     return [batched_stream(BATCHED_SEED, i, **kw) for i in range(n_streams)]
 
 

@@ -5,6 +5,8 @@ compare the HIP path's counts, per-kind statistics and record digests with
 these files, and its first/last records with the stored ones.
 
     python tests/golden/make_golden.py nbody_full growing_q1 ...
+    python tests/golden/make_golden.py batched 4      # the 256 batched streams, 4 processes
+    python tests/golden/make_golden.py serving 3      # each kind of serving session
 """
 import json
 import os
@@ -27,6 +29,7 @@ CASES = {
 }
 
 EDGE_KEEP = 2000  # first and last records stored verbatim
+BATCHED_FILE = "batched_digests.json"
 
 
 def rec_list(arr, n):
@@ -65,5 +68,66 @@ def main(names):
         print(name, st["n_instructions"], st["n_edges"], f"{doc['oracle_seconds']} s", flush=True)
 
 
+def _batched_one(i):
+    s = S.batched_stream(S.BATCHED_SEED, i, w_all=S.BATCHED_W_ALL, w_slice=S.BATCHED_W_SLICE)
+    t0 = time.time()
+    st = oracle.run_stream(s, fetch=False)
+    o = st["stats"]
+    return {"index": i, "stream": s.name, "tasks": s.n_tasks, "oracle_seconds": round(time.time() - t0, 2),
+            "n_instructions": o["n_instructions"], "n_bindings": o["n_bindings"], "n_edges": o["n_edges"],
+            "per_kind": o["per_kind"], "per_dep": o["per_dep"], "warnings": o["warnings"],
+            "digest_instructions": o["digest_instructions"], "digest_bindings": o["digest_bindings"],
+            "digest_edges": o["digest_edges"]}
+
+
+def batched(workers):
+    """Oracle statistics and digests of every stream of the batched workload
+    (256 streams), computed in parallel worker processes."""
+    from multiprocessing import Pool
+    with Pool(workers) as pool:
+        rows = []
+        for r in pool.imap_unordered(_batched_one, range(256)):
+            rows.append(r)
+            print(r["index"], r["n_instructions"], r["n_edges"], r["oracle_seconds"], flush=True)
+    rows.sort(key=lambda r: r["index"])
+    with open(os.path.join(HERE, BATCHED_FILE), "w") as f:
+        json.dump({"seed": S.BATCHED_SEED, "w_all": S.BATCHED_W_ALL, "w_slice": S.BATCHED_W_SLICE,
+                   "streams": rows}, f, indent=0)
+
+
+SERVING_FILE = "serving_digests.json"
+
+
+def serving_kinds():
+    """Every distinct session stream the serving workload draws."""
+    out = [S.stencil_1d(), S.stencil_2d(), S.nbody(steps=50)]
+    out += [S.growing(queue_cap=cap) for cap in (1, 2, 4, 8, 16, 32, 64)]
+    return out
+
+
+def _serving_one(i):
+    s = serving_kinds()[i]
+    st = oracle.run_stream(s, fetch=False)["stats"]
+    keep = ("n_instructions", "n_bindings", "n_edges", "per_kind", "per_dep", "warnings",
+            "digest_instructions", "digest_bindings", "digest_edges")
+    return s.name, {k: st[k] for k in keep}
+
+
+def serving(workers):
+    """Oracle statistics and digests of each kind of serving session, keyed by
+    stream name (sessions carry the kind's name after their session prefix)."""
+    from multiprocessing import Pool
+    with Pool(workers) as pool:
+        rows = dict(pool.map(_serving_one, range(len(serving_kinds()))))
+    with open(os.path.join(HERE, SERVING_FILE), "w") as f:
+        json.dump(rows, f, indent=1)
+    print(sorted(rows))
+
+
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(CASES))
+    if sys.argv[1:2] == ["serving"]:
+        serving(int(sys.argv[2]) if len(sys.argv) > 2 else 3)
+    elif sys.argv[1:2] == ["batched"]:
+        batched(int(sys.argv[2]) if len(sys.argv) > 2 else 4)
+    else:
+        main(sys.argv[1:] or list(CASES))

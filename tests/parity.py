@@ -43,3 +43,26 @@ def record_words(out):
     e = out["edges"]
     we = np.stack([e["from"], e["to"], e["kinds"].astype(np.uint64)], axis=1).astype(np.uint64)
     return w, wb, we
+
+
+def reader_run_stream(variant):
+    """All-reads over several chunks per device (shared read scans, runs of
+    readers), neighborhood reads that refine the grid, epochs, lookahead on
+    and off and a queue cap; variant 2 leaves one buffer uninitialised."""
+    from paper_2503_10516_amd import streams as S
+    s = S.Stream(2, 2, 16, lookahead=variant % 2, queue_cap=3 if variant == 3 else 0, name=f"reader_runs{variant}")
+    p = s.buffer(1, (512,), 8, S.INIT_HOST)
+    q = s.buffer(1, (512,), 8, S.INIT_HOST if variant != 2 else S.INIT_NONE)
+    for t in range(14):
+        s.task(1, (0,), (512,), [S.Access(p, S.READ, S.ALL), S.Access(q, S.WRITE, S.ONE_TO_ONE)])
+        if t % 3 == 0:
+            s.task(1, (0,), (512,), [S.Access(q, S.READ, S.NEIGHBORHOOD, (t + 1, 0, 0)),
+                                      S.Access(p, S.WRITE, S.ONE_TO_ONE)])
+        if t % 5 == 4:
+            s.epoch()
+        if t % 4 == 1:
+            s.task(1, (0,), (512,), [S.Access(q, S.READ, S.SLICE, slice_dim=0), S.Access(p, S.READ, S.ALL),
+                                      S.Access(q, S.READ, S.NEIGHBORHOOD, (2, 0, 0))])
+            s.task(1, (0,), (512,), [S.Access(p, S.READ_WRITE, S.ONE_TO_ONE), S.Access(q, S.READ, S.ALL)])
+    s.shutdown()
+    return s

@@ -13,7 +13,7 @@ import subprocess
 import pytest
 
 import oracle
-from parity import assert_same
+from parity import assert_same, reader_run_stream
 from paper_2503_10516_amd import binding as B
 from paper_2503_10516_amd import streams as S
 
@@ -108,3 +108,123 @@ def test_sim_capacity_error_is_reported(sim_lib):
     with pytest.raises(B.IgError) as e:
         B.run_stream(s, lib_path=sim_lib, threads=64, cap_instructions=40)
     assert e.value.status == B.IG_E_CAPACITY
+
+
+def test_sim_batch_graph_replays_identically(sim_lib):
+    streams = [S.stencil_1d(n=128, tasks=10), S.nbody_example(), S.random_small(7)]
+    ctxs = []
+    for s in streams:
+        ctx = B.make_context(s, lib_path=sim_lib, threads=64)
+        ctx.record(s)
+        ctxs.append(ctx)
+    g = B.BatchGraph(ctxs)
+    for replay in range(2):
+        g.launch()
+        for s, ctx in zip(streams, ctxs):
+            assert ctx.sync() == 0
+            assert_same(oracle.run_stream(s), ctx.fetch_all(), f"graph{replay}:{s.name}")
+    g.close()
+    B.batch_rewind(ctxs)
+    B.batch_flush(ctxs)
+    for s, ctx in zip(streams, ctxs):
+        assert ctx.sync() == 0
+        assert_same(oracle.run_stream(s), ctx.fetch_all(), "rewound:" + s.name)
+        ctx.close()
+
+
+def test_sim_progress_is_the_compiled_prefix(sim_lib):
+    """tasks_done counts the leading tasks whose records exist: every kernel
+    of a done task is emitted, no kernel of a later task is."""
+    s = S.stencil_1d(n=256, tasks=21)
+    ctx = B.make_context(s, lib_path=sim_lib, threads=64)
+    kernels_of = set()
+    prev = 0
+    for cut in (3, 9, 16, len(s.cmds) - 1, len(s.cmds)):
+        ctx.record(S.Stream(s.nodes, s.devices, s.chunks, cmds=s.cmds[prev:cut]))
+        prev = cut
+        ctx.flush()
+        assert ctx.sync() == 0
+        done, seen, err, fin, _, _ = (int(v) for v in B.batch_progress([ctx])[0])
+        assert err == 0 and done <= seen
+        assert seen == sum(1 for c in s.cmds[:cut] if c[0] == "task")
+        ins = ctx.fetch_all()["instructions"]  # records since the previous fetch
+        kernels_of |= set(int(t) for t in ins[ins["kind"] == 4]["task"])
+        assert kernels_of == set(range(done))
+        assert fin == (1 if cut == len(s.cmds) else 0)
+    assert done == seen == s.n_tasks
+    ctx.close()
+
+
+def test_sim_batch_resizes_and_matches_oracle(sim_lib):
+    """Deliberately small capacities: the batch re-creates the streams that
+    overflow, and every stream's graph is still its oracle graph."""
+    from paper_2503_10516_amd import batch as BT
+    streams = [S.nbody(n=256, steps=6, nodes=2, devices=4, chunks=8), S.stencil_1d(n=128, tasks=8),
+               S.random_small(11), S.growing(width=12, steps=10, devices=4, queue_cap=3)]
+    bt = BT.Batch(streams, threads=64, margin=0.05, floor=16, lib_path=sim_lib)
+    info = bt.size(window=5)
+    assert sum(info.values()) >= 1
+    bt.launch()
+    prog = bt.progress()
+    assert (prog[:, 2] == 0).all() and (prog[:, 3] == 1).all()
+    for s, ctx in zip(streams, bt.contexts):
+        assert ctx.sync() == 0
+        assert_same(oracle.run_stream(s), ctx.fetch_all(), "batch:" + s.name)
+    bt.close()
+
+
+def test_sim_windowed_batch_matches_oracle(sim_lib):
+    """Launches bounded to a few commands per stream give the same graphs."""
+    from paper_2503_10516_amd import batch as BT
+    streams = [S.stencil_1d(n=128, tasks=9), S.random_small(5), S.nbody_example()]
+    bt = BT.Batch(streams, threads=64, lib_path=sim_lib)
+    seen = []
+    prog = bt.analyse(range(len(streams)), window=4, log=lambda k, n, p: seen.append(n))
+    assert len(seen) > 3 and (prog[:, 2] == 0).all()
+    assert list(prog[:, 5]) == [len(s.cmds) for s in streams]
+    for s, ctx in zip(streams, bt.contexts):
+        assert ctx.sync() == 0
+        assert_same(oracle.run_stream(s), ctx.fetch_all(), "window:" + s.name)
+    bt.close()
+
+
+DIGESTS = ("n_instructions", "n_bindings", "n_edges", "digest_instructions", "digest_bindings", "digest_edges")
+
+
+def test_sim_serving_mix_equals_each_session_alone(sim_lib):
+    """Continuous batching: sessions admitted into 2 slots as they free up,
+    tasks arriving over time; every session's graph equals its oracle graph
+    (which is also what it gives alone)."""
+    from paper_2503_10516_amd import serve
+    sessions = [S.stencil_1d(n=128, tasks=10), S.nbody_example(), S.growing(width=12, steps=8, devices=4, queue_cap=2),
+                S.random_small(3), S.stencil_1d(n=64, tasks=6, lookahead=0)]
+    out = serve.Server(slots=2, threads=64, lib_path=sim_lib).run(sessions, rate=2e3)
+    assert out["tasks"] == sum(s.n_tasks for s in sessions)
+    assert out["launches"] >= 2
+    for s, st in zip(sessions, out["session_stats"]):
+        want = oracle.run_stream(s, fetch=False)["stats"]
+        alone = B.run_stream(s, lib_path=sim_lib, threads=64, fetch=False)["stats"]
+        for k in DIGESTS:
+            assert st[k] == want[k] == alone[k], (s.name, k)
+    assert out["p99_latency_us"] >= out["p50_latency_us"] > 0
+
+
+@pytest.mark.parametrize("variant", range(4))
+def test_sim_reader_runs(variant, sim_lib):
+    s = reader_run_stream(variant)
+    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), s.name)
+
+
+@pytest.mark.parametrize("index", [0, 3, 7])
+def test_sim_batched_generator_streams(index, sim_lib):
+    s = S.batched_stream(S.BATCHED_SEED, index, max_tasks=60, max_log_chunks=6, max_log_extent=12)
+    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), s.name)
+
+
+def test_sim_copies_with_many_sources_on_all_threads(sim_lib):
+    """Copies of one task are emitted by every thread of the workgroup, not
+    only by the memory workers; copies whose destination cells carry runs of
+    readers have more sources than the register set holds and stage them
+    through per-thread scratch (sized for every thread)."""
+    s = S.nbody(n=4096, steps=3, nodes=1, devices=2, chunks=64)
+    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), s.name)

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import assert_same, record_words
+from parity import assert_same, reader_run_stream, record_words
 from paper_2503_10516_amd import binding as B
 from paper_2503_10516_amd import streams as S
 
@@ -162,3 +162,91 @@ def test_batched_generator_streams_sample():
         assert ctx.sync() == 0
         assert_same(oracle.run_stream(s), ctx.fetch_all(), "batchgen:" + s.name)
         ctx.close()
+
+
+def test_batch_graph_replays_match_oracle():
+    """The captured graph (reset + batched analysis) replayed several times,
+    with eager work and synchronisations between replays: every replay gives
+    every stream its oracle graph."""
+    import torch
+    streams = [S.random_small(2000 + i) for i in range(6)] + [S.stencil_2d(side=256, tasks=24, nodes=2, devices=4,
+                                                                               chunks=16), S.nbody_example()]
+    ctxs = []
+    for s in streams:
+        ctx = B.make_context(s, threads=256)
+        ctx.record(s)
+        ctxs.append(ctx)
+    want = [oracle.run_stream(s) for s in streams]
+    g = B.BatchGraph(ctxs)
+    x = torch.arange(1 << 20, device="cuda", dtype=torch.float32)
+    for replay in range(3):
+        print(f"[gpu] graph replay {replay}", flush=True)
+        g.launch()
+        for s, ctx, w in zip(streams, ctxs, want):
+            assert ctx.sync() == 0
+            assert_same(w, ctx.fetch_all(), f"graph{replay}:{s.name}")
+        x = (x * 2 + 1).sum().expand(1 << 20).contiguous()  # eager work between replays
+        torch.cuda.synchronize()
+    prog = B.batch_progress(ctxs)
+    assert (prog[:, 2] == 0).all() and (prog[:, 3] == 1).all()
+    assert list(prog[:, 0]) == [s.n_tasks for s in streams]
+    g.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_batch_class_resizes_and_matches_oracle():
+    from paper_2503_10516_amd import batch as BT
+    streams = [S.nbody(n=4096, steps=8, nodes=4, devices=4, chunks=32), S.stencil_1d(n=512, tasks=30),
+               S.random_small(21), S.growing(width=840, steps=24, queue_cap=5)]
+    bt = BT.Batch(streams, threads=256, margin=0.05, floor=16)
+    assert sum(bt.size().values()) >= 1
+    bt.launch()
+    for s, ctx in zip(streams, bt.contexts):
+        assert ctx.sync() == 0
+        assert_same(oracle.run_stream(s), ctx.fetch_all(), "batch:" + s.name)
+    bt.close()
+
+
+DIGESTS = ("n_instructions", "n_bindings", "n_edges", "digest_instructions", "digest_bindings", "digest_edges")
+
+
+def test_serving_mix_equals_each_session_alone():
+    """Continuous batching on the device: sessions admitted into 3 slots as
+    they free up, Poisson arrivals; each session's graph equals its oracle
+    graph and its graph when analysed alone."""
+    from paper_2503_10516_amd import serve
+    sessions = [S.stencil_2d(side=512, tasks=40, nodes=2, devices=4, chunks=16), S.nbody(n=4096, steps=6, nodes=4,
+                                                                                            devices=4, chunks=32),
+                S.growing(width=840, steps=24, queue_cap=2), S.stencil_1d(n=512, tasks=30), S.random_small(31),
+                S.growing(width=840, steps=16, lookahead=0)]
+    print(f"[gpu] serving {len(sessions)} sessions", flush=True)
+    out = serve.Server(slots=3, threads=256).run(sessions, rate=2e4)
+    assert out["launches"] >= 2
+    for s, st in zip(sessions, out["session_stats"]):
+        want = oracle.run_stream(s, fetch=False)["stats"]
+        alone = B.run_stream(s, fetch=False)["stats"]
+        for k in DIGESTS:
+            assert st[k] == want[k] == alone[k], (s.name, k)
+
+
+@pytest.mark.parametrize("variant", range(4))
+def test_reader_runs(variant):
+    s = reader_run_stream(variant)
+    want, got = run_both(s)
+    assert_same(want, got, s.name)
+
+
+@pytest.mark.parametrize("threads", [64, 1024])
+def test_many_chunks_per_device(threads):
+    """Eight chunks per device: shared read scans, runs of readers, copies of
+    one device emitted by many threads."""
+    s = S.nbody(n=1 << 14, steps=6, nodes=2, devices=4, chunks=64)
+    want, got = run_both(s, threads=threads)
+    assert_same(want, got, f"{s.name}@{threads}")
+
+
+def test_copies_with_many_sources_on_all_threads():
+    s = S.nbody(n=4096, steps=3, nodes=1, devices=2, chunks=64)
+    want, got = run_both(s, threads=256)
+    assert_same(want, got, s.name)
