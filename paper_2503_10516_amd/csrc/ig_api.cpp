@@ -142,6 +142,7 @@ static u64 carve(const Caps& k, char* base, DevCtx* h, Tail* tail = nullptr) {
     TAKE(cons_off, u32, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
     TAKE(cons_cnt, u32, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
     TAKE(cons_x, u32, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
+    TAKE(k_rank, u32, (u64)MAX_CHUNKS);
     TAKE(copies, CopyRec, k.cap_unit);
     TAKE(dev_cnt, u32, k.n_dev);
     TAKE(dev_base, u32, k.n_dev);

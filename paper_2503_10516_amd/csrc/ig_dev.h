@@ -274,6 +274,7 @@ struct DevCtx {
     u32* cons_off;        // [MAX_CHUNKS * IG_MAX_ACCESS]
     u32* cons_cnt;        // [MAX_CHUNKS * IG_MAX_ACCESS]
     u32* cons_x;          // [MAX_CHUNKS * IG_MAX_ACCESS] first copy of (chunk, access) within its device
+    u32* k_rank;          // [MAX_CHUNKS] kernel index of a chunk within its device (NONE: empty)
     CopyRec* copies;      // [cap_unit]
     u32* dev_cnt;         // [n_dev] copies per device, then kernels per device
     u32* dev_base;        // [n_dev]

@@ -39,6 +39,7 @@ struct Shared {
     u32 t_dims, t_nacc, t_id, t_cmd;
     u32 t_stamps;  // some write may leave its chunk's dim-0 range: check overlaps cell by cell
     u64 t_wbufs;   // buffers the task writes (bit per buffer)
+    u32 t_par;     // kernels may be emitted in parallel (see kernels_emit_par)
     i64 t_lo[3], t_hi[3];
     u32 n_alloc_instr, n_new_allocs, n_copies, n_kernels;
     u32 win_first, win_n;  // lookahead window (queue positions)
@@ -221,11 +222,17 @@ IGD void rd_each(const DevCtx& c, u32 head, F f) {
             }
         }
 }
+// Take a block: from the memory's free list, else a fresh one.  Several
+// threads may take blocks of one memory at once (reader additions split by
+// cell); blocks are never returned to a free list in the same phase, so a
+// compare-and-swap pop cannot see a recycled head.
 IGD u32 rb_alloc(DevCtx& c, Shared& sh, u32 m) {
-    u32 h = c.rb_free[m];
-    if (h) {
-        c.rb_free[m] = c.rb[h * 8 + 7];
-        return h;
+    u32 h = atomicAdd(&c.rb_free[m], 0u);
+    while (h) {
+        const u32 nx = c.rb[h * 8 + 7];
+        const u32 seen = atomicCAS(&c.rb_free[m], h, nx);
+        if (seen == h) return h;
+        h = seen;
     }
     u32 i = atomicAdd(&sh.s.rb_top, 1u);
     if (i >= c.cap_rb) {
@@ -540,6 +547,63 @@ IGD void stage(DevCtx& c, Shared& sh, u32 x, SrcSet& s) {
         }
     c.tab_off[slot] = off;
     c.tab_cnt[slot] = n;
+}
+
+// Stage the union of a source set and a sorted, duplicate-free list (the
+// shared sources of a read group): a two-pointer merge, counted first so the
+// staging slot is exact.
+IGN void stage_merge_lists(DevCtx& c, Shared& sh, u32 x, const u64* a, u32 na, const u64* b, u32 nb) {
+    const u32 slot = x - sh.unit_first;
+    u32 n = 0;
+    for (u32 i = 0, j = 0; i < na || j < nb; ++n) {
+        const u64 ia = i < na ? a[i] >> 8 : ~0ull, jb = j < nb ? b[j] >> 8 : ~0ull;
+        if (ia <= jb) ++i;
+        if (jb <= ia) ++j;
+    }
+    const u32 off = atomicAdd(&sh.stage_top, n);
+    if ((u64)off + n > (u64)c.cap_unit * 8 || slot >= c.cap_unit) {
+        cap_error(sh, IG_CAP_UNIT);
+        return;
+    }
+    u32 o = off;
+    for (u32 i = 0, j = 0; i < na || j < nb; ++o) {
+        const u64 ia = i < na ? a[i] >> 8 : ~0ull, jb = j < nb ? b[j] >> 8 : ~0ull;
+        u32 kind = 0;
+        u32 from;
+        if (ia <= jb) {
+            kind |= (u32)(a[i] & 0xFF);
+            from = (u32)ia;
+            ++i;
+        }
+        if (jb <= ia) {
+            kind |= (u32)(b[j] & 0xFF);
+            from = (u32)jb;
+            ++j;
+        }
+        c.stage_from[o] = from;
+        c.stage_kind[o] = (u8)kind;
+        c.has_succ[from] = 1;
+    }
+    c.tab_off[slot] = off;
+    c.tab_cnt[slot] = n;
+}
+
+IGD void stage_with_list(DevCtx& c, Shared& sh, u32 x, SrcSet& s, const u64* list, u32 nlist) {
+    if (nlist == 0) {
+        stage(c, sh, x, s);
+        return;
+    }
+    if (s.spilled) {
+        const u32 n = src_dedup(s.g.buf, s.g.aux, s.g.n);
+        stage_merge_lists(c, sh, x, s.g.buf, n, list, nlist);
+        return;
+    }
+    // the register set goes through the worker's list (sorted already)
+    u64* buf = s.g.buf;
+#pragma unroll
+    for (u32 i = 0; i < REG_SRC; ++i)
+        if (i < s.n) buf[i] = s.r[i];
+    stage_merge_lists(c, sh, x, buf, s.n, list, nlist);
 }
 
 // ===========================================================================
@@ -1724,6 +1788,10 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                 u32 rv[REG_NEED];
                 u32 n = 0;
                 bool big = false;
+                bool ordered = true;  // keys seen in non-decreasing order (then no sort is needed)
+                u64 last_key = 0;
+                // the last source allocation found, reused while cells stay inside it
+                u32 l_pm = NONE, l_src = 0, l_lo[3] = {0, 0, 0}, l_hi[3] = {0, 0, 0};
                 for (u32 i0 = r.clo[0]; i0 < r.chi[0]; ++i0)
                     for (u32 i1 = r.clo[1]; i1 < r.chi[1]; ++i1)
                         for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2) {
@@ -1735,9 +1803,27 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                             if (!any) continue;  // never initialised: nothing to copy
                             const u32 pm = pmv[cell];
                             const u32 p = eff_w(sh, prod[cell]);
-                            const u32 src = live_containing_cell(c, b, pm, i0, i1, i2);
-                            if (src == 0) set_error(sh, IG_E_DEVICE);
+                            u32 src;
+                            if (pm == l_pm && i0 >= l_lo[0] && i0 < l_hi[0] && i1 >= l_lo[1] && i1 < l_hi[1] &&
+                                i2 >= l_lo[2] && i2 < l_hi[2]) {
+                                src = l_src;
+                            } else {
+                                src = live_containing_cell(c, b, pm, i0, i1, i2);
+                                if (src == 0) {
+                                    set_error(sh, IG_E_DEVICE);
+                                } else {
+                                    const DAlloc& sa = c.allocs[src];
+                                    l_pm = pm;
+                                    l_src = src;
+                                    for (u32 t3 = 0; t3 < 3; ++t3) {
+                                        l_lo[t3] = sa.clo[t3];
+                                        l_hi[t3] = sa.chi[t3];
+                                    }
+                                }
+                            }
                             u64 x = ((u64)pm << 56) | ((u64)p << 24) | (u64)(src & 0xFFFFFF);
+                            if (x < last_key) ordered = false;
+                            last_key = x;
                             if (!big && n == REG_NEED) {
 #pragma unroll
                                 for (u32 i = 0; i < REG_NEED; ++i) {
@@ -1783,7 +1869,7 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                 const u64* gk;
                 const u32* gv;
                 if (big) {
-                    msort_kv(key, val, key2, val2, n);
+                    if (!ordered) msort_kv(key, val, key2, val2, n);
                     gk = key;
                     gv = val;
                 } else {
@@ -1905,7 +1991,7 @@ IGD void rd_group_flush(DevCtx& c, Shared& sh, u32 m, RdGroup& g) {
     g.n = 0;
 }
 
-IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
+IGN void kernels_emit_seq(DevCtx& c, Shared& sh, u32 kern_first) {
     const u32 A = sh.t_nacc, K = c.per_dev;
     for (u32 m = tid(); m < c.n_mem; m += nt()) {
         if (m < 2) continue;
@@ -1935,6 +2021,8 @@ IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
             SrcSet s;
             ss_init(c, s);
             u32 grouped = 0;  // accesses handled by a read group
+            const u64* glist = nullptr;  // one group's shared sources, merged at staging
+            u32 nglist = 0;
             for (u32 j = 0; j < A; ++j) {
                 if (!al[j]) continue;
                 const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
@@ -1945,7 +2033,12 @@ IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
                     RdGroup& g = grp[j];
                     u64* src = c.wk_rsrc + ((size_t)tid() * RD_CACHE + j) * c.cap_src;
                     if (g.n && g.first + g.n == x && same_cells(g, al[j], rg)) {
-                        for (u32 i = 0; i < g.nsrc; ++i) ss_add(sh, s, (u32)(src[i] >> 8), (u32)(src[i] & 0xFF));
+                        if (!glist) {
+                            glist = src;
+                            nglist = g.nsrc;
+                        } else {
+                            for (u32 i = 0; i < g.nsrc; ++i) ss_add(sh, s, (u32)(src[i] >> 8), (u32)(src[i] & 0xFF));
+                        }
                         ++g.n;
                         continue;
                     }
@@ -1964,7 +2057,12 @@ IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
                     } else {
                         ns = src_dedup(src, t.g.aux, t.g.n);
                     }
-                    for (u32 i = 0; i < ns; ++i) ss_add(sh, s, (u32)(src[i] >> 8), (u32)(src[i] & 0xFF));
+                    if (!glist) {
+                        glist = src;
+                        nglist = ns;
+                    } else {
+                        for (u32 i = 0; i < ns; ++i) ss_add(sh, s, (u32)(src[i] >> 8), (u32)(src[i] & 0xFF));
+                    }
                     g.alloc = al[j];
                     g.first = x;
                     g.n = 1;
@@ -1980,7 +2078,7 @@ IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
                     if (mode & IG_WRITE) cell_write_edge(c, sh, s, e);
                 });
             }
-            stage(c, sh, x, s);
+            stage_with_list(c, sh, x, s, glist, nglist);
             // reads first, then writes (a cell both read and written ends written)
             for (u32 j = 0; j < A; ++j) {
                 const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
@@ -2015,6 +2113,125 @@ IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
     }
 }
 
+// The same records when every access to a buffer the task writes stays in its
+// chunk's dim-0 range.  Then no cell is touched by two kernels of the task
+// unless both only read it, so every kernel sees the task's starting state on
+// the cells it accesses (reads see writers, which only the cell's own chunk
+// changes; writes see readers, which no other chunk adds to written cells),
+// and its edges and writes do not depend on the others.
+//  1. any thread takes any kernel: record, bindings, edges, writes;
+//  2. reader additions, split by cell among the threads of each device, in
+//     kernel order per cell (a cell the kernel itself wrote gets no reader).
+IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
+    const u32 A = sh.t_nacc, K = c.per_dev, C = c.chunks;
+    // kernel rank of each chunk within its device (empty chunks have none)
+    for (u32 d = tid(); d < c.n_dev; d += nt()) {
+        u32 r = 0;
+        for (u32 k = d * K; k < (d + 1) * K; ++k) {
+            i64 k0, k1;
+            chunk_range(c, sh.t_lo[0], sh.t_hi[0], k, k0, k1);
+            const bool empty = k0 >= k1 || sh.t_lo[1] >= sh.t_hi[1] || sh.t_lo[2] >= sh.t_hi[2];
+            c.k_rank[k] = empty ? NONE : r++;
+        }
+    }
+    bar();
+    for (u32 k = tid(); k < C; k += nt()) {
+        const u32 rk = c.k_rank[k];
+        if (rk == NONE) continue;
+        const u32 d = k / K, m = d + 2;
+        i64 lo[3] = {0, sh.t_lo[1], sh.t_lo[2]};
+        i64 hi[3] = {0, sh.t_hi[1], sh.t_hi[2]};
+        chunk_range(c, sh.t_lo[0], sh.t_hi[0], k, lo[0], hi[0]);
+        const u32 x = kern_first + c.kdev_base[d] + rk;
+        const u64 bi = sh.s.n_binds + (u64)(c.kdev_base[d] + rk) * A;
+        put_instr(c, x, IG_KERNEL, 0, sh.t_id, k, NONE, m, 0xFFFF, 0, 0, lo, hi);
+        u32 al[IG_MAX_ACCESS];
+        for (u32 j = 0; j < A; ++j) {
+            const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
+            al[j] = rg.empty ? 0 : live_containing(c, rg.buffer, m, rg.lo, rg.hi);
+            if (!rg.empty && al[j] == 0) set_error(sh, IG_E_DEVICE);
+            c.b_instr[bi + j] = x;
+            c.b_access[bi + j] = j;
+            c.b_alloc[bi + j] = al[j];
+        }
+        SrcSet s;
+        ss_init(c, s);
+        for (u32 j = 0; j < A; ++j) {
+            if (!al[j]) continue;
+            const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
+            const DAlloc& a = c.allocs[al[j]];
+            const u32 mode = rg.mode;
+            scan_cells(am_cells(c, a), a, rg.clo, rg.chi, [&](const AmCell& e, AmCell*) {
+                if (mode & IG_READ) cell_read_edge(sh, s, e);
+                if (mode & IG_WRITE) cell_write_edge(c, sh, s, e);
+            });
+        }
+        stage(c, sh, x, s);
+        for (u32 j = 0; j < A; ++j) {
+            const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
+            if (!al[j] || !(rg.mode & IG_WRITE)) continue;
+            const DAlloc& a = c.allocs[al[j]];
+            const DBuf& B = c.bufs[rg.buffer];
+            u32* prod = W32(c, B.prod_off);
+            u32* pmv = W32(c, B.pm_off);
+            u64* mask = W64(c, B.mask_off);
+            scan_cells(am_cells(c, a), a, rg.clo, rg.chi,
+                       [&](const AmCell& e, AmCell* p) { cell_set_writer_at(c, m, p, e, x); });
+            for (u32 i0 = rg.clo[0]; i0 < rg.chi[0]; ++i0)
+                for (u32 i1 = rg.clo[1]; i1 < rg.chi[1]; ++i1)
+                    for (u32 i2 = rg.clo[2]; i2 < rg.chi[2]; ++i2) {
+                        const u32 cell = cell_of(B, i0, i1, i2);
+                        prod[cell] = x;
+                        pmv[cell] = m;
+                        for (u32 w = 0; w < c.mw; ++w)
+                            mask[(size_t)cell * c.mw + w] = (w == (m >> 6)) ? (1ull << (m & 63)) : 0ull;
+                    }
+        }
+    }
+    bar();
+    // reader additions: the threads t with t % n_dev == d share device d's
+    // cells by allocation-local index
+    const u32 nd = c.n_dev, t = tid();
+    const u32 d0 = nt() >= nd ? t % nd : t;
+    const u32 dstep = nt() >= nd ? nd : nt();
+    const u32 g = nt() >= nd ? t / nd : 0;
+    const u32 G = nt() >= nd ? (nt() - d0 + nd - 1) / nd : 1;
+    for (u32 d = d0; d < nd; d += dstep) {
+        if (nt() >= nd && d != d0) break;
+        const u32 m = d + 2;
+        for (u32 k = d * K; k < (d + 1) * K; ++k) {
+            const u32 rk = c.k_rank[k];
+            if (rk == NONE) continue;
+            const u32 x = kern_first + c.kdev_base[d] + rk;
+            for (u32 j = 0; j < A; ++j) {
+                const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
+                if (rg.empty || !(rg.mode & IG_READ)) continue;
+                const u32 al = live_containing(c, rg.buffer, m, rg.lo, rg.hi);
+                if (!al) continue;
+                const DAlloc& a = c.allocs[al];
+                AmCell* cl = am_cells(c, a);
+                const u32 n1 = rg.chi[1] - rg.clo[1], n2 = rg.chi[2] - rg.clo[2];
+                const u32 total = (rg.chi[0] - rg.clo[0]) * n1 * n2;
+                for (u32 q = 0; q < total; ++q) {
+                    const u32 i2 = q % n2, i1 = (q / n2) % n1, i0 = q / (n1 * n2);
+                    const u32 l = alloc_local(a, rg.clo[0] + i0, rg.clo[1] + i1, rg.clo[2] + i2);
+                    if (l % G != g) continue;
+                    const AmCell e = am_load(cl + l);
+                    if ((e.w & ~W_ALLOC) == x) continue;  // written by this kernel: no reader remains
+                    cell_add_reader_at(c, sh, m, cl + l, e, x);
+                }
+            }
+        }
+    }
+}
+
+IGN void kernels_emit(DevCtx& c, Shared& sh, u32 kern_first) {
+    if (uniform(sh.t_par))
+        kernels_emit_par(c, sh, kern_first);
+    else
+        kernels_emit_seq(c, sh, kern_first);
+}
+
 // ===========================================================================
 // Compile one task: allocation phase, coherence copies, kernels, edges.
 // ===========================================================================
@@ -2044,6 +2261,20 @@ IGN void load_task(DevCtx& c, Shared& sh, u32 ci) {
         }
         sh.t_stamps = stamps;
         sh.t_wbufs = wb;
+        // parallel kernel emission: every access to a written buffer stays in
+        // its chunk's dim-0 range, and no pure read covers a region shared by
+        // the chunks of a device (those share one scan in the ordered path)
+        u32 par = 1;
+        for (u32 j = 0; j < cmd.task.n_access; ++j) {
+            const ig_access& a = cmd.task.access[j];
+            const bool confined = a.mapper == IG_MAP_ONE_TO_ONE || (a.mapper == IG_MAP_SLICE && a.slice_dim != 0) ||
+                                  (a.mapper == IG_MAP_NEIGHBORHOOD && a.radius[0] == 0);
+            const bool allish = a.mapper == IG_MAP_ALL || a.mapper == IG_MAP_FIXED ||
+                                (a.mapper == IG_MAP_SLICE && a.slice_dim == 0);
+            if (((wb >> a.buffer) & 1) && !confined) par = 0;
+            if (a.mode == IG_READ && !((wb >> a.buffer) & 1) && allish) par = 0;
+        }
+        sh.t_par = par;
     }
     bar();
 }
