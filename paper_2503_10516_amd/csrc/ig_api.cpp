@@ -135,7 +135,7 @@ static u64 carve(const Caps& k, char* base, DevCtx* h, Tail* tail = nullptr) {
     TAKE(heap, u32, k.cap_heap);
     TAKE(heap_free, u32, 32);
     TAKE(rb, u32, (u64)k.cap_rb * 8);
-    TAKE(rb_free, u32, k.n_mem);
+    TAKE(rb_free, u64, k.n_mem);
     TAKE(reg, Region, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
     TAKE(chunk_lo, i64, MAX_CHUNKS);
     TAKE(chunk_hi, i64, MAX_CHUNKS);

@@ -266,7 +266,7 @@ struct DevCtx {
     u32* heap;        // [cap_heap] words
     u32* heap_free;   // [32] free-list heads per size class
     u32* rb;          // [cap_rb * 8] reader blocks
-    u32* rb_free;     // [n_mem] free-list heads per memory
+    u64* rb_free;         // [n_mem] free reader blocks per memory: tag << 32 | head
     // --- per-command scratch ---
     Region* reg;          // [MAX_CHUNKS * IG_MAX_ACCESS]
     i64* chunk_lo;        // [MAX_CHUNKS]

@@ -222,17 +222,18 @@ IGD void rd_each(const DevCtx& c, u32 head, F f) {
             }
         }
 }
-// Take a block: from the memory's free list, else a fresh one.  Several
-// threads may take blocks of one memory at once (reader additions split by
-// cell); blocks are never returned to a free list in the same phase, so a
-// compare-and-swap pop cannot see a recycled head.
+// Free lists of reader blocks, one per memory: a 64-bit head (tag << 32 |
+// block) changed only by compare-and-swap, the tag counting every change, so
+// that threads taking and returning blocks of one memory at once cannot be
+// fooled by a head that was taken and returned in between.
 IGD u32 rb_alloc(DevCtx& c, Shared& sh, u32 m) {
-    u32 h = atomicAdd(&c.rb_free[m], 0u);
-    while (h) {
-        const u32 nx = c.rb[h * 8 + 7];
-        const u32 seen = atomicCAS(&c.rb_free[m], h, nx);
-        if (seen == h) return h;
-        h = seen;
+    u64 old = atomicAdd(&c.rb_free[m], 0ull);
+    while ((u32)old) {
+        const u32 h = (u32)old;
+        const u64 nw = (((old >> 32) + 1) << 32) | c.rb[h * 8 + 7];
+        const u64 seen = atomicCAS(&c.rb_free[m], old, nw);
+        if (seen == old) return h;
+        old = seen;
     }
     u32 i = atomicAdd(&sh.s.rb_top, 1u);
     if (i >= c.cap_rb) {
@@ -242,15 +243,26 @@ IGD u32 rb_alloc(DevCtx& c, Shared& sh, u32 m) {
     return i;
 }
 
+IGD bool rd_put(DevCtx& c, u32 h, u32 x) {
+    u32* blk = c.rb + h * 8;
+    for (u32 s = 0; s < RB_SLOTS; ++s)
+        if (blk[s] == NONE) {
+            blk[s] = x;
+            return true;
+        }
+    return false;
+}
+
+IGN void rd_compact(DevCtx& c, Shared& sh, u32 m, u32* head);
+
 IGD void rd_append(DevCtx& c, Shared& sh, u32 m, u32* head, u32 x) {
-    const u32 h = *head;
-    if (h) {
-        u32* blk = c.rb + h * 8;
-        for (u32 s = 0; s < RB_SLOTS; ++s)
-            if (blk[s] == NONE) {
-                blk[s] = x;
-                return;
-            }
+    u32 h = *head;
+    if (h && rd_put(c, h, x)) return;
+    if (h && c.rb[h * 8 + 7]) {
+        // a second block is due: first drop what no longer matters
+        rd_compact(c, sh, m, head);
+        h = *head;
+        if (h && rd_put(c, h, x)) return;
     }
     const u32 n = rb_alloc(c, sh, m);
     if (!n) return;
@@ -261,19 +273,17 @@ IGD void rd_append(DevCtx& c, Shared& sh, u32 m, u32* head, u32 x) {
     *head = n;
 }
 
-// Return a list to its memory's free list.  Any thread may do this (the
-// whole chain is spliced in with one compare-and-swap); blocks are taken from
-// the free list only by the memory's owner, in other phases.
+// Return a list to its memory's free list (the whole chain at once).
 IGD void rd_clear(DevCtx& c, u32 m, u32* head) {
     const u32 first = *head;
     if (!first) return;
     u32 last = first;
     while (c.rb[last * 8 + 7]) last = c.rb[last * 8 + 7];
-    u32 old = atomicAdd(&c.rb_free[m], 0u);
+    u64 old = atomicAdd(&c.rb_free[m], 0ull);
     while (true) {
-        c.rb[last * 8 + 7] = old;
+        c.rb[last * 8 + 7] = (u32)old;
         __threadfence_block();
-        const u32 seen = atomicCAS(&c.rb_free[m], old, first);
+        const u64 seen = atomicCAS(&c.rb_free[m], old, (((old >> 32) + 1) << 32) | first);
         if (seen == old) break;
         old = seen;
     }
@@ -311,6 +321,44 @@ IGN u32 rd_copy(DevCtx& c, Shared& sh, u32 m, u32 head) {
             rd_append_range(c, sh, m, &out, first, n);
     });
     return out;
+}
+
+// Rewrite a reader list keeping only what still matters: readers before the
+// last epoch go, readers before the synchronisation point S all read as S
+// and are kept as one entry S (S only grows and stays below later epochs
+// exactly when they do, so the substitution is exact for the future too).
+IGN void rd_compact(DevCtx& c, Shared& sh, u32 m, u32* head) {
+    const u32 S = sh.s.S, E = sh.s.E;
+    u32 out = 0;
+    bool has_s = false;
+    auto put = [&](u32 first, u32 n) {
+        if (n == 1) {
+            if (!(out && rd_put(c, out, first))) {
+                const u32 b = rb_alloc(c, sh, m);
+                if (!b) return;
+                u32* blk = c.rb + b * 8;
+                blk[0] = first;
+                for (u32 q = 1; q < RB_SLOTS; ++q) blk[q] = NONE;
+                blk[7] = out;
+                out = b;
+            }
+        } else {
+            rd_append_range(c, sh, m, &out, first, n);
+        }
+    };
+    rd_each(c, *head, [&](u32 first, u32 n) {
+        const u32 end = first + n;
+        u32 lo = first < E ? E : first;
+        if (lo >= end) return;
+        if (lo < S) {
+            has_s = true;
+            lo = S;
+        }
+        if (lo < end) put(lo, end - lo);
+    });
+    if (has_s) put(S, 1);
+    rd_clear(c, m, head);
+    *head = out;
 }
 
 // Lazy horizon/epoch substitution (Sec. 3.5): ids below the synchronisation
@@ -421,6 +469,7 @@ IGD void src_add(Shared& sh, Src& s, u32 id, u32 kind) {
 // The sources of one instruction: up to 16 in registers (sorted by id, kinds
 // OR-ed), spilling to the worker's global list beyond that.
 constexpr u32 REG_SRC = 16;
+constexpr u32 SS_RECENT = 8;
 struct SrcSet {
     u64 r[REG_SRC];
     u32 n;
@@ -428,6 +477,9 @@ struct SrcSet {
     Src g;
     // the last reader run added (cells of one region often share it)
     u32 run_first, run_n, run_kind;
+    // once spilled: the last entries appended, to skip repeats cheaply
+    u64 recent[SS_RECENT];
+    u32 recent_pos;
 };
 
 IGD Src worker_src(DevCtx& c);
@@ -452,8 +504,16 @@ IGD void ss_init_buf(SrcSet& s, u64* buf, u64* aux, u32 cap) {
 
 IGD void ss_add(Shared& sh, SrcSet& s, u32 id, u32 kind) {
     if (s.spilled) {
-        // consecutive cells mostly repeat the previous source
-        if (s.g.n && s.g.buf[s.g.n - 1] == (((u64)id << 8) | kind)) return;
+        // neighbouring cells mostly repeat recent sources
+        const u64 key = ((u64)id << 8) | kind;
+        bool seen = false;
+#pragma unroll
+        for (u32 i = 0; i < SS_RECENT; ++i) seen = seen || s.recent[i] == key;
+        if (seen) return;
+#pragma unroll
+        for (u32 i = 0; i < SS_RECENT; ++i)
+            if (i == s.recent_pos) s.recent[i] = key;  // static indices keep the ring in registers
+        s.recent_pos = (s.recent_pos + 1) % SS_RECENT;
         src_add(sh, s.g, id, kind);
         return;
     }
@@ -470,6 +530,9 @@ IGD void ss_add(Shared& sh, SrcSet& s, u32 id, u32 kind) {
         for (u32 i = 0; i < REG_SRC; ++i) s.g.buf[i] = s.r[i];
         s.g.n = REG_SRC;
         s.spilled = true;
+#pragma unroll
+        for (u32 i = 0; i < SS_RECENT; ++i) s.recent[i] = ~0ull;
+        s.recent_pos = 0;
         src_add(sh, s.g, id, kind);
         return;
     }
@@ -1079,18 +1142,22 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
         const u32 on1a = sv.chi[1] - sv.clo[1], on2a = sv.chi[2] - sv.clo[2];
         AmCell* cells = am_cells(c, a);
         AmCell* ocl = (AmCell*)(c.heap + sv.buffer);
+        // Refinement only splits cells: the first new cell of an old cell
+        // takes over its reader list, the other parts get copies.
         u32 l = 0;
-        for (u32 i0 = a.clo[0]; i0 < a.chi[0]; ++i0)
-            for (u32 i1 = a.clo[1]; i1 < a.chi[1]; ++i1)
+        for (u32 i0 = a.clo[0]; i0 < a.chi[0]; ++i0) {
+            const bool f0 = i0 == a.clo[0] || r0[i0 - 1] != r0[i0];
+            for (u32 i1 = a.clo[1]; i1 < a.chi[1]; ++i1) {
+                const bool f1 = i1 == a.clo[1] || r1[i1 - 1] != r1[i1];
                 for (u32 i2 = a.clo[2]; i2 < a.chi[2]; ++i2, ++l) {
+                    const bool f2 = i2 == a.clo[2] || r2[i2 - 1] != r2[i2];
                     const u32 ol = ((r0[i0] - sv.clo[0]) * on1a + (r1[i1] - sv.clo[1])) * on2a + (r2[i2] - sv.clo[2]);
                     AmCell e = am_load(ocl + ol);
-                    e.ov = rd_copy(c, sh, a.mem, e.ov);
+                    if (!(f0 && f1 && f2) && e.ov) e.ov = rd_copy(c, sh, a.mem, e.ov);
                     cells[l] = e;
                 }
-        const u32 ocells = (sv.chi[0] - sv.clo[0]) * on1a * on2a;
-        for (u32 ol = 0; ol < ocells; ++ol)
-            if (ocl[ol].ov) rd_clear(c, a.mem, &ocl[ol].ov);
+            }
+        }
     }
     bar();
     if (tid() == 0) {
@@ -1489,14 +1556,13 @@ IGD void cell_init(AmCell* p, u32 w) {
 }
 
 IGD void free_edges(DevCtx& c, Shared& sh, SrcSet& s, const DAlloc& a) {
-    const AmCell* cells = am_cells(c, a);
-    for (u32 l = 0; l < a.ncells; ++l) cell_free_edges(c, sh, s, am_load(cells + l));
+    scan_cells(am_cells(c, a), a, a.clo, a.chi, [&](const AmCell& e, AmCell*) { cell_free_edges(c, sh, s, e); });
 }
 
 IGN void release_readers(DevCtx& c, const DAlloc& a) {
-    AmCell* cells = am_cells(c, a);
-    for (u32 l = 0; l < a.ncells; ++l)
-        if (cells[l].ov) rd_clear(c, a.mem, &cells[l].ov);
+    scan_cells(am_cells(c, a), a, a.clo, a.chi, [&](const AmCell& e, AmCell* p) {
+        if (e.ov) rd_clear(c, a.mem, &p->ov);
+    });
 }
 
 IGD void live_remove(DevCtx& c, u32 b, u32 m, u32 id) {
@@ -1629,19 +1695,14 @@ IGN void alloc_phase(DevCtx& c, Shared& sh) {
                         put_instr(c, xc, IG_COPY, IG_F_RESIZE, sh.t_id, NONE, b, m, m, nid, absorb[q], lo, hi);
                         SrcSet s;
                         ss_init(c, s);
-                        for (u32 i0 = a0; i0 < a1; ++i0)
-                            for (u32 i1 = b0; i1 < b1; ++i1)
-                                for (u32 i2 = c0; i2 < c1; ++i2) {
-                                    cell_read_edge(sh, s, am_load(ocl + alloc_local(old, i0, i1, i2)));
-                                    cell_write_edge(c, sh, s, am_load(ncl + alloc_local(na, i0, i1, i2)));
-                                }
+                        const u32 blo[3] = {a0, b0, c0}, bhi[3] = {a1, b1, c1};
+                        scan_cells(ocl, old, blo, bhi, [&](const AmCell& e, AmCell*) { cell_read_edge(sh, s, e); });
+                        scan_cells(ncl, na, blo, bhi, [&](const AmCell& e, AmCell*) { cell_write_edge(c, sh, s, e); });
                         stage(c, sh, xc, s);
-                        for (u32 i0 = a0; i0 < a1; ++i0)
-                            for (u32 i1 = b0; i1 < b1; ++i1)
-                                for (u32 i2 = c0; i2 < c1; ++i2) {
-                                    cell_add_reader(c, sh, m, ocl + alloc_local(old, i0, i1, i2), xc);
-                                    cell_set_writer(c, m, ncl + alloc_local(na, i0, i1, i2), xc);
-                                }
+                        scan_cells(ocl, old, blo, bhi,
+                                   [&](const AmCell& e, AmCell* p) { cell_add_reader_at(c, sh, m, p, e, xc); });
+                        scan_cells(ncl, na, blo, bhi,
+                                   [&](const AmCell& e, AmCell* p) { cell_set_writer_at(c, m, p, e, xc); });
                     });
                 }
                 for (u32 q = 0; q < nabs; ++q) {
@@ -2740,7 +2801,7 @@ IGN void destroy_buffer(DevCtx& c, Shared& sh, u32 b) {
 IGN void init_state(DevCtx& c, Shared& sh) {
     // I0, the initial epoch, and empty tables
     for (u32 i = tid(); i < 32; i += nt()) c.heap_free[i] = 0;
-    for (u32 i = tid(); i < c.n_mem; i += nt()) c.rb_free[i] = 0;
+    for (u32 i = tid(); i < c.n_mem; i += nt()) c.rb_free[i] = 0ull;
     if (tid() == 0) {
         Scalars& s = sh.s;
         s.n_instr = 1;

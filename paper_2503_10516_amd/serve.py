@@ -59,6 +59,7 @@ class _Session:
         self.done = 0
         self.ctx: Optional[B.Context] = None
         self.pending = False  # recorded commands not yet analysed
+        self.recorded = 0     # commands recorded into the context
         self.stats: Optional[Dict[str, object]] = None
 
 
@@ -84,7 +85,11 @@ class Server:
     and an arena memory budget."""
 
     def __init__(self, slots: int = 64, threads: int = 256, mem_budget: int = 96 << 30,
-                 lib_path: Optional[str] = None):
+                 lib_path: Optional[str] = None, window: int = 16):
+        # window: commands per session per launch (0: all pending); short
+        # launches report completions often and keep one long session from
+        # holding back the others
+        self.window = window
         self.slots = slots
         self.threads = threads
         self.mem_budget = mem_budget
@@ -118,6 +123,7 @@ class Server:
                 s.ctx = B.make_context(s.stream, lib_path=self.lib_path, threads=self.threads, **s.caps)
                 for c in s.prefix:
                     s.ctx.record_command(c)
+                s.recorded = len(s.prefix)
                 s.pending = True
                 mem_used += s.bytes
                 active.append(s)
@@ -134,6 +140,7 @@ class Server:
                 s.ctx.submit_desc(s.descs[s.submitted])
                 for c in unit[1:]:
                     s.ctx.record_command(c)
+                s.recorded += len(unit)
                 s.submitted += 1
                 s.pending = True
                 next_arr += 1
@@ -154,6 +161,8 @@ class Server:
                     if d > s.done:
                         s.done_at[s.done:d] = t_done
                         s.done = d
+                    if p[5] < s.recorded:
+                        s.pending = True
                     if p[3] == 1 and s.done == s.n_tasks:
                         if keep_stats:
                             s.stats = s.ctx.stats()
@@ -165,7 +174,7 @@ class Server:
                 admit(t_done)
             ready = [s for s in active if s.pending]
             if ready:
-                B.batch_flush([s.ctx for s in ready])
+                B.batch_flush([s.ctx for s in ready], window=self.window)
                 if host:
                     ev = _HostEvent()
                 else:

@@ -228,3 +228,12 @@ def test_sim_copies_with_many_sources_on_all_threads(sim_lib):
     through per-thread scratch (sized for every thread)."""
     s = S.nbody(n=4096, steps=3, nodes=1, devices=2, chunks=64)
     assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), s.name)
+
+
+@pytest.mark.parametrize("cap,lookahead", [(0, 1), (1, 1), (3, 1), (8, 1), (0, 0)])
+def test_sim_growing_reader_lists(cap, lookahead, sim_lib):
+    """Rows read by every later task: reader lists grow and are compacted
+    (readers before the last epoch dropped, those before the sync point kept
+    as one entry) while grid refinement copies them."""
+    s = S.growing(width=24, steps=48, devices=4, queue_cap=cap, lookahead=lookahead)
+    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), s.name)
