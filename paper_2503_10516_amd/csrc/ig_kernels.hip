@@ -255,11 +255,24 @@ IGD bool rd_put(DevCtx& c, u32 h, u32 x) {
 
 IGN void rd_compact(DevCtx& c, Shared& sh, u32 m, u32* head);
 
+// the newest block of a list holds a reader that now reads as S or absent
+IGD bool rd_stale_head(const DevCtx& c, const Shared& sh, u32 h) {
+    bool stale = false;
+    for (u32 q = 0; q < RB_SLOTS; ++q) {
+        const u32 v = c.rb[h * 8 + q];
+        if (v == NONE) continue;
+        stale = stale || (v & ~RB_RANGE) < sh.s.S;
+        if (v & RB_RANGE) ++q;
+    }
+    return stale;
+}
+
 IGD void rd_append(DevCtx& c, Shared& sh, u32 m, u32* head, u32 x) {
     u32 h = *head;
     if (h && rd_put(c, h, x)) return;
-    if (h && c.rb[h * 8 + 7]) {
-        // a second block is due: first drop what no longer matters
+    if (h && c.rb[h * 8 + 7] && rd_stale_head(c, sh, h)) {
+        // a further block is due and even the newest readers have aged:
+        // first drop what no longer matters
         rd_compact(c, sh, m, head);
         h = *head;
         if (h && rd_put(c, h, x)) return;
