@@ -2219,7 +2219,9 @@ IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
         const u32 x = kern_first + c.kdev_base[d] + rk;
         const u64 bi = sh.s.n_binds + (u64)(c.kdev_base[d] + rk) * A;
         put_instr(c, x, IG_KERNEL, 0, sh.t_id, k, NONE, m, 0xFFFF, 0, 0, lo, hi);
-        u32 al[IG_MAX_ACCESS];
+        // per-thread allocation ids in LDS (the coherence keys are free in
+        // this phase): a private array indexed by access would live in scratch
+        u32* al = reinterpret_cast<u32*>(sh.wkey) + tid() * IG_MAX_ACCESS;
         for (u32 j = 0; j < A; ++j) {
             const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
             al[j] = rg.empty ? 0 : live_containing(c, rg.buffer, m, rg.lo, rg.hi);
