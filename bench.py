@@ -133,6 +133,11 @@ def run_batched(args):
     prog = bt.progress()
     assert (prog[:, 2] == 0).all() and (bt.counts() == cnt).all()
     wall = min(walls)
+    # roofline of the batched launch: the same per-record algorithmic bytes
+    # as the single stream, over every stream, against the launch's time
+    ab = int(74 * cnt[:, 0].sum() + 12 * cnt[:, 1].sum() + 9 * cnt[:, 2].sum()
+             + sum(64 * len(ss[i].cmds) + 80 * sum(len(c[1].accesses) for c in ss[i].cmds if c[0] == "task")
+                   for i in range(len(ss))))
     lat = np.concatenate([(lambda x: (x[:, 1] - x[:, 0]) / 1e3)(c.task_times_ns()) for c in bt.contexts])
     # the plain single-stream path on a sample: every 16th stream by weight
     sample = bt.order[::16]
@@ -156,6 +161,8 @@ def run_batched(args):
         "streams": len(ss), "tasks": int(cnt[:, 3].sum()), "instructions": int(cnt[:, 0].sum()),
         "edges": int(cnt[:, 2].sum()), "records": records,
         "value": records / wall, "unit": "records/s", "wall_s": wall, "kernel_s": kernel_s,
+        "roofline": {"bound": "hbm", "achieved": ab / kernel_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": ab / kernel_s / 1e9 / PEAK_HBM_GBS, "algorithmic_bytes": ab},
         "graph_launches": args.batch_steps,
         "p50_task_latency_us": float(np.percentile(lat, 50)), "p99_task_latency_us": float(np.percentile(lat, 99)),
         "threads_per_stream": threads, "autotune": tuned, "resized": grown,

@@ -250,3 +250,21 @@ def test_copies_with_many_sources_on_all_threads():
     s = S.nbody(n=4096, steps=3, nodes=1, devices=2, chunks=64)
     want, got = run_both(s, threads=256)
     assert_same(want, got, s.name)
+
+
+def test_windowed_batch_matches_oracle():
+    """Launches bounded to a few commands per stream, then a graph replay."""
+    from paper_2503_10516_amd import batch as BT
+    streams = [S.stencil_2d(side=256, tasks=20, nodes=2, devices=4, chunks=32), S.random_small(41),
+               S.growing(width=840, steps=20, queue_cap=3)]
+    bt = BT.Batch(streams, threads=256)
+    prog = bt.analyse(range(len(streams)), window=5)
+    assert (prog[:, 2] == 0).all() and list(prog[:, 5]) == [len(s.cmds) for s in streams]
+    for s, ctx in zip(streams, bt.contexts):
+        assert ctx.sync() == 0
+        assert_same(oracle.run_stream(s), ctx.fetch_all(), "window:" + s.name)
+    bt.launch()
+    for s, ctx in zip(streams, bt.contexts):
+        assert ctx.sync() == 0
+        assert_same(oracle.run_stream(s), ctx.fetch_all(), "replay:" + s.name)
+    bt.close()
