@@ -1996,8 +1996,12 @@ IGN void coherence_emit(DevCtx& c, Shared& sh, u32 copy_first) {
     // stale cell is copied once), their source cells are up to date where
     // they are read and so are no copy's destination, and readers of the
     // sources go to the owners' inboxes.  Any thread takes any copy.
-    const u32 n = sh.copy_top;
-    for (u32 q = tid(); q < n; q += nt()) {
+    // Each thread takes a contiguous block of copies: neighbouring copies
+    // mostly go to the same memory, and the lanes of a wave would otherwise
+    // all return reader blocks to that memory's free list at once.
+    const u32 n = sh.copy_top, per = (n + nt() - 1) / nt();
+    const u32 q0 = tid() * per, q1 = q0 + per < n ? q0 + per : n;
+    for (u32 q = q0; q < q1; ++q) {
         const CopyRec& cr = c.copies[q];
         const u32 m = cr.dst_mem, idx = cr.pad0;
         const u32 x = copy_first + c.dev_base[m - 2] + c.cons_x[idx] + (q - c.cons_off[idx]);
@@ -2209,7 +2213,10 @@ IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
         }
     }
     bar();
-    for (u32 k = tid(); k < C; k += nt()) {
+    // kernel i of the walk is chunk k of device i mod n_dev: the lanes of a
+    // wave work on different devices (and free lists)
+    for (u32 i = tid(); i < C; i += nt()) {
+        const u32 k = (i % c.n_dev) * K + i / c.n_dev;
         const u32 rk = c.k_rank[k];
         if (rk == NONE) continue;
         const u32 d = k / K, m = d + 2;
