@@ -237,3 +237,9 @@ def test_sim_growing_reader_lists(cap, lookahead, sim_lib):
     as one entry) while grid refinement copies them."""
     s = S.growing(width=24, steps=48, devices=4, queue_cap=cap, lookahead=lookahead)
     assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), s.name)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run(["python3", os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "exactly one GPU" in r.stdout
