@@ -272,7 +272,13 @@ ig_status ig_batch_flush(ig_context* const* ctxs, size_t n, void* stream);
 ig_status ig_batch_flush_window(ig_context* const* ctxs, size_t n, void* stream, uint32_t max_commands);
 
 /* Forget the analysis results of n contexts (as ig_rewind) with one kernel
- * launch on the stream (NULL = the first context's stream). */
+ * launch on the stream (NULL = the first context's stream).
+ *
+ * The batched calls (ig_batch_flush, _window, _rewind, _progress) write the
+ * table of context pointers into the first context's staging area and wait
+ * for the stream before reusing it.  Errors: IG_E_INVALID (no contexts, a
+ * NULL context, or contexts built with different `threads`), IG_E_CAPACITY
+ * (more contexts than the staging area holds), IG_E_DEVICE. */
 ig_status ig_batch_rewind(ig_context* const* ctxs, size_t n, void* stream);
 
 /* Progress of n contexts, gathered on the device and copied back in one
