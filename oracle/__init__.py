@@ -64,7 +64,16 @@ class Stats(ctypes.Structure):
                 ("per_dep", ctypes.c_uint64 * 5), ("resizes", ctypes.c_uint64),
                 ("warnings", ctypes.c_uint64), ("tasks_submitted", ctypes.c_uint64),
                 ("tasks_rejected", ctypes.c_uint64), ("digest_instructions", ctypes.c_uint64),
-                ("digest_bindings", ctypes.c_uint64), ("digest_edges", ctypes.c_uint64)]
+                ("digest_bindings", ctypes.c_uint64), ("digest_edges", ctypes.c_uint64),
+                ("u_w", ctypes.c_uint64), ("u_r", ctypes.c_uint64), ("u_b", ctypes.c_uint64),
+                ("map_boxes", ctypes.c_uint64)]
+
+
+# command trace (igo_event): every call reaching the command stream, in order
+EV_BUFFER, EV_TASK, EV_REJECTED, EV_HORIZON, EV_EPOCH, EV_DESTROY, EV_SHUTDOWN = 1, 2, 3, 4, 5, 6, 7
+EVENT_DTYPE = np.dtype([("kind", "<u4"), ("arg", "<u4"), ("allocating", "<u4"), ("compiled_at", "<u4"),
+                        ("n_instr", "<u8")])
+assert EVENT_DTYPE.itemsize == 24
 
 
 def build(force: bool = False) -> str:
@@ -101,6 +110,10 @@ def lib() -> ctypes.CDLL:
                      "igo_fetch_task_status"):
             getattr(L, name).argtypes = [c_ctx, ctypes.c_void_p, ctypes.c_size_t, P(ctypes.c_size_t)]
         L.igo_stats_get.argtypes = [c_ctx, P(Stats)]
+        L.igo_fetch_events.argtypes = [c_ctx, ctypes.c_void_p, ctypes.c_size_t, P(ctypes.c_size_t)]
+        L.igo_fetch_events.restype = ctypes.c_int32
+        L.igo_event_count.argtypes = [c_ctx]
+        L.igo_event_count.restype = ctypes.c_size_t
         L.igo_box_subtract.argtypes = [P(Box), P(Box), P(Box)]
         L.igo_box_subtract.restype = ctypes.c_size_t
         L.igo_box_merges.argtypes = [P(Box), P(Box)]
@@ -219,6 +232,9 @@ class OracleContext:
             status=self._fetch(self.L.igo_fetch_task_status, np.dtype("<i4"), nt),
         )
 
+    def events(self) -> np.ndarray:
+        return self._fetch(self.L.igo_fetch_events, EVENT_DTYPE, self.L.igo_event_count(self.h))
+
     def stats(self) -> Dict[str, object]:
         s = Stats()
         self.L.igo_stats_get(self.h, ctypes.byref(s))
@@ -253,6 +269,7 @@ def run_stream(stream, fetch: bool = True) -> Dict[str, object]:
     out: Dict[str, object] = {"rcs": rcs, "seconds": elapsed, "stats": ctx.stats()}
     if fetch:
         out.update(ctx.fetch_all())
+        out["events"] = ctx.events()
     ctx.close()
     return out
 

@@ -454,6 +454,7 @@ struct Req {
 struct Cmd {
     bool horizon;
     TaskCmd task;
+    uint32_t event;  // index of the trace event that pushed it
 };
 
 struct Access {
@@ -486,10 +487,25 @@ struct igo_context {
     std::map<std::pair<uint32_t, uint16_t>, std::vector<Box>> plan;
     std::vector<int32_t> task_status;
     uint64_t n_tasks = 0, rejected = 0, warnings = 0, resizes = 0;
+    uint64_t u_w = 0, u_r = 0, u_b = 0, map_boxes = 0;  // algorithmic-bytes terms (igo_stats)
+    std::vector<igo_event> events;                      // command trace (igo_event)
+    uint32_t cur_event = NONE;
     bool finished = false;
     size_t cur_instr = 0, cur_bind = 0, cur_edge = 0, cur_status = 0;
 
     // ----- small helpers -----
+    uint32_t begin_event(uint32_t kind, uint32_t arg) {
+        igo_event e;
+        std::memset(&e, 0, sizeof e);
+        e.kind = kind;
+        e.arg = arg;
+        e.compiled_at = NONE;
+        e.n_instr = instrs.size();
+        events.push_back(e);
+        cur_event = (uint32_t)(events.size() - 1);
+        return cur_event;
+    }
+
     uint16_t mem_of_chunk(uint32_t k) const { return (uint16_t)(2 + k / per_dev); }
     uint32_t node_of_mem(uint16_t m) const { return (uint32_t)(m - 2) / devices; }
 
@@ -570,6 +586,10 @@ struct igo_context {
     // reads and writes ends up written.
     void access_apply(uint32_t x, const std::vector<Access>& accs) {
         for (const Access& a : accs) {
+            if (a.mode & IGO_READ) ++u_r;
+            if (a.mode & IGO_WRITE) ++u_w;
+        }
+        for (const Access& a : accs) {
             if (!(a.mode & IGO_READ)) continue;
             std::vector<AllocEntry> out;
             for (const AllocEntry& e : allocs[a.alloc].map) {
@@ -616,6 +636,7 @@ struct igo_context {
     }
 
     void mask_add(uint32_t b, const Box& r, uint16_t m) {
+        ++u_b;
         std::vector<BufEntry> out;
         for (const BufEntry& e : buffers[b].map) {
             Box in = intersect(e.box, r);
@@ -637,6 +658,7 @@ struct igo_context {
     }
 
     void buffer_assign(uint32_t b, const Box& r, uint32_t producer, uint16_t m) {
+        ++u_b;
         std::vector<BufEntry> out;
         for (const BufEntry& e : buffers[b].map) {
             if (!intersects(e.box, r)) {
@@ -697,6 +719,7 @@ struct igo_context {
                 na.box = nb;
                 na.alive = true;
                 const uint32_t ai = emit(IGO_ALLOC, 0, t.id, NONE, b, m, NONE16, na.id, 0, nb);
+                ++u_w;  // the new map starts with the ALLOC as writer of the whole box
                 AllocEntry e0;
                 e0.box = nb;
                 e0.writer = ai;
@@ -880,6 +903,7 @@ struct igo_context {
     }
 
     void compile(const Cmd& c, const std::deque<Cmd>& behind) {
+        events[c.event].compiled_at = cur_event;
         if (c.horizon)
             compile_horizon();
         else
@@ -914,6 +938,7 @@ struct igo_context {
             return;
         }
         const bool alloc = !c.horizon && is_allocating(c.task);
+        if (!c.horizon) events[c.event].allocating = alloc ? 1 : 0;
         if (queue.empty() && !alloc) {
             compile(c, std::deque<Cmd>());
             return;
@@ -1049,6 +1074,7 @@ int32_t igo_buffer_create(igo_context* c, uint32_t dims, const int64_t extent[3]
     b.alive = true;
     b.user_alloc = 0;
     const uint32_t id = (uint32_t)c->buffers.size();
+    c->begin_event(IGO_EV_BUFFER, id);
     BufEntry e;
     e.box = b.whole();
     e.mask.reset();
@@ -1084,6 +1110,7 @@ int32_t igo_buffer_create(igo_context* c, uint32_t dims, const int64_t extent[3]
 
 int32_t igo_buffer_destroy(igo_context* c, uint32_t b) {
     if (!c || c->finished || b >= c->buffers.size() || !c->buffers[b].alive) return IGO_E_INVALID;
+    c->begin_event(IGO_EV_DESTROY, b);
     c->destroy_buffer(b);
     return IGO_OK;
 }
@@ -1128,6 +1155,7 @@ int32_t igo_submit_task(igo_context* c, const igo_task_desc* td, uint64_t* out_t
             }
             t.regions[k].push_back(rg);
         }
+        if (!is_empty(t.chunks[k])) c->map_boxes += td->n_access;
     }
     // Sec. 4.4: writes of different chunks (devices) must not overlap.  Sort
     // each buffer's write boxes by their start in dimension 0 and compare
@@ -1144,6 +1172,7 @@ int32_t igo_submit_task(igo_context* c, const igo_task_desc* td, uint64_t* out_t
         for (size_t i = 0; i < v.size(); ++i)
             for (size_t j = i + 1; j < v.size() && v[j].first.lo[0] < v[i].first.hi[0]; ++j)
                 if (v[i].second != v[j].second && intersects(v[i].first, v[j].first)) {
+                    c->begin_event(IGO_EV_REJECTED, t.id);
                     c->task_status.push_back(IGO_E_OVERLAPPING_WRITE);
                     ++c->rejected;
                     return IGO_E_OVERLAPPING_WRITE;
@@ -1166,11 +1195,13 @@ int32_t igo_submit_task(igo_context* c, const igo_task_desc* td, uint64_t* out_t
     Cmd cmd;
     cmd.horizon = false;
     cmd.task = t;
+    cmd.event = c->begin_event(IGO_EV_TASK, t.id);
     c->push_command(cmd);
     if (++c->tasks_since_sync == c->horizon_step) {
         c->tasks_since_sync = 0;
         Cmd h;
         h.horizon = true;
+        h.event = c->begin_event(IGO_EV_HORIZON, NONE);
         c->push_command(h);
     }
     return status;
@@ -1178,6 +1209,7 @@ int32_t igo_submit_task(igo_context* c, const igo_task_desc* td, uint64_t* out_t
 
 int32_t igo_epoch(igo_context* c) {
     if (!c || c->finished) return IGO_E_INVALID;
+    c->begin_event(IGO_EV_EPOCH, NONE);
     c->emit_epoch();
     return IGO_OK;
 }
@@ -1185,6 +1217,7 @@ int32_t igo_epoch(igo_context* c) {
 int32_t igo_shutdown(igo_context* c) {
     if (!c) return IGO_E_INVALID;
     if (c->finished) return IGO_OK;
+    c->begin_event(IGO_EV_SHUTDOWN, NONE);
     for (uint32_t b = 0; b < c->buffers.size(); ++b)
         if (c->buffers[b].alive) c->destroy_buffer(b);
     c->emit_epoch();
@@ -1216,6 +1249,13 @@ int32_t igo_fetch_task_status(igo_context* c, int32_t* dst, size_t cap, size_t* 
     return c ? fetch(c->task_status, c->cur_status, dst, cap, n) : IGO_E_INVALID;
 }
 
+int32_t igo_fetch_events(igo_context* c, igo_event* dst, size_t cap, size_t* n) {
+    size_t cursor = 0;
+    return c ? fetch(c->events, cursor, dst, cap, n) : IGO_E_INVALID;
+}
+
+size_t igo_event_count(igo_context* c) { return c ? c->events.size() : 0; }
+
 uint64_t igo_digest(const uint64_t* words, size_t n_records, size_t wpr) {
     uint64_t sum = 0;
     for (size_t i = 0; i < n_records; ++i)
@@ -1237,6 +1277,10 @@ int32_t igo_stats_get(igo_context* c, igo_stats* s) {
     s->warnings = c->warnings;
     s->tasks_submitted = c->n_tasks;
     s->tasks_rejected = c->rejected;
+    s->u_w = c->u_w;
+    s->u_r = c->u_r;
+    s->u_b = c->u_b;
+    s->map_boxes = c->map_boxes;
     uint64_t sum = 0, w[12];
     for (size_t i = 0; i < c->instrs.size(); ++i) {
         instruction_words(c->instrs[i], w);

@@ -143,7 +143,42 @@ typedef struct igo_stats {
     uint64_t digest_instructions;
     uint64_t digest_bindings;
     uint64_t digest_edges;
+    /* Terms of the algorithmic-bytes model of the measurement (one count per
+     * access, independent of how an implementation fragments its maps):
+     *   u_w        allocation-map writer updates: one per ALLOC (its whole
+     *              box) and per write access of a COPY or KERNEL (Sec. 3.2)
+     *   u_r        allocation-map reader insertions: one per read access of a
+     *              COPY or KERNEL
+     *   u_b        buffer-map updates: one per coherence COPY (its box joins
+     *              the destination's up-to-date memories, Sec. 3.3) and per
+     *              KERNEL write (new original producer)
+     *   map_boxes  range-mapper evaluations: non-empty chunks x accessors of
+     *              every structurally valid task (Sec. 2.1, Sec. 3.1) */
+    uint64_t u_w;
+    uint64_t u_r;
+    uint64_t u_b;
+    uint64_t map_boxes;
 } igo_stats;
+
+/* One entry of the command trace: every call that reaches the command stream
+ * (buffer creation, task, the horizon the stream inserts, epoch, buffer
+ * destruction, shutdown), in call order.  Tests use it to check the Sec. 4.3
+ * queue decisions (the allocating predicate and the moment each command is
+ * compiled) against an independent brute force. */
+#define IGO_EV_BUFFER 1
+#define IGO_EV_TASK 2      /* accepted task, pushed to the command queue */
+#define IGO_EV_REJECTED 3  /* task rejected by the Sec. 4.4 overlap check */
+#define IGO_EV_HORIZON 4
+#define IGO_EV_EPOCH 5
+#define IGO_EV_DESTROY 6
+#define IGO_EV_SHUTDOWN 7
+typedef struct igo_event {
+    uint32_t kind;         /* IGO_EV_* */
+    uint32_t arg;          /* buffer id (BUFFER, DESTROY), task id (TASK, REJECTED), else NONE */
+    uint32_t allocating;   /* TASK with lookahead on: the allocating predicate at push time */
+    uint32_t compiled_at;  /* TASK, HORIZON: index of the event during which it was compiled */
+    uint64_t n_instr;      /* instructions emitted when the event began */
+} igo_event; /* 24 bytes */
 
 typedef struct igo_context igo_context;
 
@@ -163,6 +198,8 @@ int32_t igo_fetch_bindings(igo_context* ctx, igo_binding* dst, size_t cap, size_
 int32_t igo_fetch_edges(igo_context* ctx, igo_edge* dst, size_t cap, size_t* n_out);
 int32_t igo_fetch_task_status(igo_context* ctx, int32_t* dst, size_t cap, size_t* n_out);
 int32_t igo_stats_get(igo_context* ctx, igo_stats* out);
+int32_t igo_fetch_events(igo_context* ctx, igo_event* dst, size_t cap, size_t* n_out);
+size_t igo_event_count(igo_context* ctx);
 
 /* box-set primitives, exported so that tests can pin them against brute force */
 size_t igo_box_subtract(const igo_box* a, const igo_box* b, igo_box* out /* >= 6 */);

@@ -25,6 +25,19 @@ and test what any correct instruction graph must satisfy.
     instruction ids are a topological order (Sec. 4.1).
   * Debug checks (Sec. 4.4): overlapping writes of different chunks are
     rejected; reads outside the initialised region warn.
+  * Resizes (Sec. 3.2): the resize copies out of an old allocation move
+    exactly its elements that are up to date on its memory, each once.
+
+Two checks restate a rule element by element, as a second formulation next
+to the oracle's box maps, because the paper fixes them only as principles:
+
+  * Exact edges (the dependency legend of the IDAG figure, Sec. 3.6): every
+    edge and every kind bit on it is justified by some element of some
+    allocation (last writer, readers since the last write, allocation
+    lifetime), and no justified edge is missing.
+  * The command queue (Sec. 4.3), replayed from the oracle's command trace:
+    the allocating predicate of every task and the moment every command is
+    compiled.
 
 The chunk split and the range mappers are evaluated here too (per element),
 straight from their definitions.
@@ -298,6 +311,7 @@ def check_stream(stream, out, n_random_orders: int = 2, seed: int = 0) -> Dict[s
                                      data=np.full(ext, V_HOST, dtype=np.int64), alive=True)
         freed = set()
         resizing = set()
+        resize_copied: Dict[int, set] = {}  # old allocation -> elements its resize copies moved
         utd = [None] * len(bufs)
         for b, (dims, ext, init) in enumerate(bufs):
             u = np.zeros(tuple(ext) + (256,), dtype=bool)
@@ -330,6 +344,15 @@ def check_stream(stream, out, n_random_orders: int = 2, seed: int = 0) -> Dict[s
                 a = int(r["alloc"])
                 _require(a in allocs and allocs[a]["alive"], f"I{x}: free of dead alloc {a}")
                 _require(allocs[a]["mem"] >= 2, "user memory is never freed")
+                if full_checks and a in resizing:
+                    # Sec. 3.2: a resize moves exactly the data of the old
+                    # allocation that is up to date on its memory
+                    od = allocs[a]
+                    want = {p for p in box_points(od["box"]) if utd[od["buffer"]][p + (od["mem"],)]}
+                    got = resize_copied.get(a, set())
+                    _require(got == want, f"I{x}: resize copies out of alloc {a} move {len(got)} elements, "
+                                          f"{len(want)} are up to date there (missing {sorted(want - got)[:4]}, "
+                                          f"extra {sorted(got - want)[:4]})")
                 allocs[a]["alive"] = False
                 freed.add(a)
                 resizing.discard(a)
@@ -349,6 +372,11 @@ def check_stream(stream, out, n_random_orders: int = 2, seed: int = 0) -> Dict[s
                     if resize:
                         _require(sa["mem"] == da["mem"], "resize copies stay on one memory")
                         _require(box_contains(da["box"], sa["box"]), "allocations never shrink")
+                        _require(s in resizing, f"I{x}: resize copy out of alloc {s}, which no new allocation covers")
+                        moved = resize_copied.setdefault(s, set())
+                        for p in box_points(box):
+                            _require(p not in moved, f"I{x}: element {p} of alloc {s} moved twice by its resize")
+                            moved.add(p)
                     else:
                         dm = da["mem"]
                         inter = (sa["mem"] >= 2 and (sa["mem"] - 2) // stream.devices != (dm - 2) // stream.devices)
@@ -502,4 +530,315 @@ def check_stream(stream, out, n_random_orders: int = 2, seed: int = 0) -> Dict[s
         _require(len(order) == n, "graph is acyclic")
         run(order, False)
     counts["races_checked"] = len(accesses)
+    counts["edges_exact"] = check_edges_exact(stream, out, tasks, bind_of)
+    if stream.cmds and stream.cmds[-1][0] == "shutdown":
+        counts["queue_commands"] = check_queue(stream, out, tasks)
     return counts
+
+
+# ---------------------------------------------------------------------------
+# Exact edge sets: every edge is justified, element by element
+# ---------------------------------------------------------------------------
+EV_BUFFER, EV_TASK, EV_REJECTED, EV_HORIZON, EV_EPOCH, EV_DESTROY, EV_SHUTDOWN = 1, 2, 3, 4, 5, 6, 7
+
+
+class _AllocMap:
+    """Per-element allocation map: last writer and, per reader, the elements
+    it has read since the last write (boolean masks over the allocation)."""
+
+    def __init__(self, box, writer):
+        self.lo = box[0]
+        self.shape = tuple(box[1][d] - box[0][d] for d in range(3))
+        self.writer = np.full(self.shape, writer, dtype=np.int64)
+        self.readers: Dict[int, np.ndarray] = {}
+
+    def mask(self, box):
+        m = np.zeros(self.shape, dtype=bool)
+        sl = tuple(slice(box[0][d] - self.lo[d], box[1][d] - self.lo[d]) for d in range(3))
+        m[sl] = True
+        return m
+
+
+def check_edges_exact(stream, out, tasks, bind_of) -> int:
+    """Every instruction's incoming edges, with their kind bits, are exactly
+    those its accesses justify on some element of some allocation (the
+    dependency legend of the IDAG figure, Sec. 3.6, with Sec. 3.2/3.3):
+
+      * a read of an element: from its last writer -- TRUE, or LIFETIME when
+        that writer is the allocation's ALLOC;
+      * a write of an element: from every instruction that read it since its
+        last write (ANTI); with no such reader, from the last writer (OUTPUT,
+        or LIFETIME for the ALLOC);
+      * a FREE: from every writer and reader of the allocation (LIFETIME);
+      * no justified edge at all: one SYNC edge from the latest epoch or
+        applied horizon.
+    Everything is evaluated against the state before the instruction; ids
+    older than the applied horizon read as that horizon, and an epoch replaces
+    every writer and forgets every reader (Sec. 3.5).  Horizons and epochs are
+    checked against the execution front elsewhere."""
+    ins = out["instructions"]
+    n = len(ins)
+    events = out.get("events")
+    _require(events is not None, "the exact edge check needs the command trace")
+    kind_of = [int(k) for k in ins["kind"]]
+    preds: List[Dict[int, int]] = [dict() for _ in range(n)]
+    for e in out["edges"]:
+        preds[int(e["to"])][int(e["from"])] = int(e["kinds"])
+    # user allocations on M0: the copies that read them name them
+    user_alloc = {}
+    for r in ins:
+        if int(r["kind"]) == COPY and int(r["src_mem"]) == 0:
+            user_alloc[int(r["buffer"])] = int(r["src_alloc"])
+    buf_ext = [c[2] for c in stream.cmds if c[0] == "buffer"]
+    created_at = {}  # instruction count -> buffers created before that instruction
+    for ev in events:
+        if int(ev["kind"]) == EV_BUFFER:
+            created_at.setdefault(int(ev["n_instr"]), []).append(int(ev["arg"]))
+    maps: Dict[int, _AllocMap] = {}
+    S, pending = 0, None
+
+    def dep(w, data_kind):
+        return DEP_LIFETIME if kind_of[w] == ALLOC else data_kind
+
+    checked = 0
+    for x in range(n):
+        for b in created_at.get(x, []):
+            if b in user_alloc:
+                maps[user_alloc[b]] = _AllocMap(((0, 0, 0), tuple(buf_ext[b])), S)
+        r = ins[x]
+        kind = kind_of[x]
+        if kind == HORIZON:
+            if pending is not None:
+                P = pending
+                for am in maps.values():
+                    am.writer[am.writer < P] = P
+                    old = [q for q in am.readers if q < P]
+                    if old:
+                        merged = am.readers.get(P, np.zeros(am.shape, dtype=bool)).copy()
+                        for q in old:
+                            merged |= am.readers.pop(q)
+                        am.readers[P] = merged
+                S = P
+            pending = x
+            continue
+        if kind == EPOCH:
+            if x > 0:
+                for am in maps.values():
+                    am.writer[...] = x
+                    am.readers.clear()
+                S, pending = x, None
+            continue
+        want: Dict[int, int] = {}
+        if kind == ALLOC:
+            maps[int(r["alloc"])] = _AllocMap(rec_box(r), x)
+        elif kind == FREE:
+            am = maps.pop(int(r["alloc"]))
+            for w in np.unique(am.writer):
+                want[int(w)] = want.get(int(w), 0) | DEP_LIFETIME
+            for q, msk in am.readers.items():
+                if msk.any():
+                    want[q] = want.get(q, 0) | DEP_LIFETIME
+        else:
+            if kind == COPY:
+                box = rec_box(r)
+                accs = [(int(r["src_alloc"]), box, READ), (int(r["alloc"]), box, WRITE)]
+            else:  # KERNEL
+                t, k = int(r["task"]), int(r["chunk"])
+                tk, _, _, _, regions = tasks[t]
+                accs = [(bind_of[x][j], regions[k][j], a.mode) for j, a in enumerate(tk.accesses)
+                        if bind_of.get(x, {}).get(j, 0) != 0]
+            staged = []
+            for a, box, mode in accs:
+                am = maps[a]
+                m = am.mask(box)
+                if mode & READ:
+                    for w in np.unique(am.writer[m]):
+                        want[int(w)] = want.get(int(w), 0) | dep(int(w), DEP_TRUE)
+                if mode & WRITE:
+                    read_any = np.zeros(am.shape, dtype=bool)
+                    for q, msk in am.readers.items():
+                        hit = msk & m
+                        if hit.any():
+                            want[q] = want.get(q, 0) | DEP_ANTI
+                            read_any |= hit
+                    for w in np.unique(am.writer[m & ~read_any]):
+                        if int(w) != x:
+                            want[int(w)] = want.get(int(w), 0) | dep(int(w), DEP_OUTPUT)
+                staged.append((am, m, mode))
+            for am, m, mode in staged:  # reads are recorded before writes
+                if mode & READ:
+                    am.readers[x] = am.readers.get(x, np.zeros(am.shape, dtype=bool)) | m
+            for am, m, mode in staged:
+                if mode & WRITE:
+                    am.writer[m] = x
+                    for q in list(am.readers):
+                        am.readers[q] = am.readers[q] & ~m
+                        if not am.readers[q].any():
+                            del am.readers[q]
+        if not want:
+            want = {S: DEP_SYNC}
+        _require(preds[x] == want, f"I{x} ({['', 'ALLOC', 'COPY', 'FREE', 'KERNEL'][kind]}): edges "
+                                   f"{sorted(preds[x].items())}, justified {sorted(want.items())}")
+        checked += 1
+    return checked
+
+
+# ---------------------------------------------------------------------------
+# The command queue of Sec. 4.3, simulated from the command trace
+# ---------------------------------------------------------------------------
+def _merge_components(boxes):
+    """Replace boxes that merge (brute-force relation: shared points or axis
+    neighbours) by their bounding box until none merge."""
+    v = [b for b in boxes if not box_empty(b)]
+    changed = True
+    while changed:
+        changed = False
+        for i in range(len(v)):
+            for j in range(i + 1, len(v)):
+                a, b = v[i], v[j]
+                far = any(max(a[0][d], b[0][d]) > min(a[1][d], b[1][d]) for d in range(3))
+                if not far and points_merge(a, b):
+                    v[i] = (tuple(min(a[0][d], b[0][d]) for d in range(3)),
+                            tuple(max(a[1][d], b[1][d]) for d in range(3)))
+                    del v[j]
+                    changed = True
+                    break
+            if changed:
+                break
+    return v
+
+
+def check_queue(stream, out, tasks) -> int:
+    """The lookahead queue (Sec. 4.3) replayed from the command trace.
+
+    A command is allocating when one of its requirements (the bounding box of
+    a (chunk, accessor) region on the chunk's memory) lies in no single box
+    of V(m, b): the allocations live at that moment, or -- while allocating
+    commands touching (m, b) are queued -- the merge components of those
+    allocations and the queued requirements.  A command compiles at once when
+    the queue is empty and it is not allocating; otherwise it is queued, and
+    the queue flushes once flush_horizons horizons were queued after the last
+    allocating command, when it holds queue_cap commands, or at an epoch, a
+    buffer destruction or shutdown.  Live allocations come from the emitted
+    ALLOC/FREE records before the command; the trace says which event
+    compiled each command, and this must match the replay."""
+    ev = out["events"]
+    ins = out["instructions"]
+    nb = sum(1 for c in stream.cmds if c[0] == "buffer")
+    # the trace follows the stream: horizons every horizon_step accepted tasks
+    seq = []
+    since = 0
+    for c in stream.cmds:
+        if c[0] == "buffer":
+            seq.append(EV_BUFFER)
+        elif c[0] == "task":
+            seq.append(None)  # accepted or rejected
+        elif c[0] == "epoch":
+            seq.append(EV_EPOCH)
+        elif c[0] == "destroy":
+            seq.append(EV_DESTROY)
+        elif c[0] == "shutdown":
+            seq.append(EV_SHUTDOWN)
+    kinds = [int(e["kind"]) for e in ev]
+    i = 0
+    for want in seq:
+        _require(i < len(kinds), "command trace ends early")
+        if want is None:
+            _require(kinds[i] in (EV_TASK, EV_REJECTED), f"event {i}: expected a task, got {kinds[i]}")
+            if kinds[i] == EV_TASK:
+                since += 1
+                if since == stream.horizon_step:
+                    since = 0
+                    i += 1
+                    _require(kinds[i] == EV_HORIZON, f"event {i}: a horizon after {stream.horizon_step} tasks")
+        else:
+            _require(kinds[i] == want, f"event {i}: expected {want}, got {kinds[i]}")
+            if want in (EV_EPOCH, EV_SHUTDOWN):
+                since = 0
+        i += 1
+    _require(i == len(kinds), "command trace has extra events")
+    del nb
+    # allocation records, for the live set at any moment
+    alloc_rec = {}
+    free_at = {}
+    for r in ins:
+        if int(r["kind"]) == ALLOC:
+            alloc_rec[int(r["alloc"])] = (int(r["id"]), int(r["buffer"]), int(r["mem"]), rec_box(r))
+        elif int(r["kind"]) == FREE:
+            free_at[int(r["alloc"])] = int(r["id"])
+
+    def live_at(n_instr):
+        live: Dict[Tuple[int, int], list] = {}
+        for a, (aid, b, m, box) in alloc_rec.items():
+            if aid < n_instr and free_at.get(a, 1 << 62) >= n_instr:
+                live.setdefault((b, m), []).append(box)
+        return live
+
+    per_dev = stream.chunks // (stream.nodes * stream.devices)
+
+    def requirements(t):
+        tk, _, _, chunks, regions = tasks[t]
+        reqs = []
+        for k, ch in enumerate(chunks):
+            if box_empty(ch):
+                continue
+            for a, rg in zip(tk.accesses, regions[k]):
+                if not box_empty(rg):
+                    reqs.append((a.buffer, 2 + k // per_dev, rg))
+        return reqs
+
+    expect_alloc = {}
+    expect_compiled = {}
+    queue = []          # event indices
+    queued_reqs = []    # requirements of queued allocating commands
+    h = 0
+
+    def flush(at):
+        nonlocal queue, queued_reqs, h
+        for q in queue:
+            expect_compiled[q] = at
+        queue, queued_reqs, h = [], [], 0
+
+    for i, e in enumerate(ev):
+        k = kinds[i]
+        if k in (EV_TASK, EV_HORIZON):
+            if not stream.lookahead:
+                expect_alloc[i] = 0
+                expect_compiled[i] = i
+                continue
+            alloc = False
+            reqs = []
+            if k == EV_TASK:
+                reqs = requirements(int(e["arg"]))
+                live = live_at(int(e["n_instr"]))
+                for b, m, box in reqs:
+                    planned = [q[2] for q in queued_reqs if q[0] == b and q[1] == m]
+                    V = live.get((b, m), [])
+                    if queue and planned:
+                        V = _merge_components(V + planned)
+                    if not any(box_contains(v, box) for v in V):
+                        alloc = True
+                expect_alloc[i] = int(alloc)
+            if not queue and not alloc:
+                expect_compiled[i] = i
+                continue
+            queue.append(i)
+            if alloc:
+                h = 0
+                queued_reqs += reqs
+            elif k == EV_HORIZON:
+                h += 1
+            if h >= stream.flush_horizons or (stream.queue_cap and len(queue) >= stream.queue_cap):
+                flush(i)
+        elif k in (EV_EPOCH, EV_DESTROY, EV_SHUTDOWN):
+            flush(i)
+    _require(not queue, "commands left in the queue after shutdown")
+    for i, e in enumerate(ev):
+        if kinds[i] == EV_TASK and stream.lookahead:
+            _require(int(e["allocating"]) == expect_alloc[i],
+                     f"event {i} (task {int(e['arg'])}): allocating {int(e['allocating'])}, "
+                     f"brute force {expect_alloc[i]}")
+        if kinds[i] in (EV_TASK, EV_HORIZON):
+            _require(int(e["compiled_at"]) == expect_compiled[i],
+                     f"event {i}: compiled during event {int(e['compiled_at'])}, brute force {expect_compiled[i]}")
+    return len(expect_compiled)

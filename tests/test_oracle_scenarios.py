@@ -117,3 +117,51 @@ def test_closed_form_nbody_reduced():
     out = oracle.run_stream(S.nbody(steps=6), fetch=False)
     assert out["stats"]["n_instructions"] == closed_form_nbody(6, 128)
     assert closed_form_nbody(500, 128) == 8240764
+
+
+def group_order_stream():
+    """Three devices on one node, one host-initialised buffer of 12 elements.
+    Tasks 0 and 1 give the devices whole-buffer allocations in the order M3,
+    M4, then M2 (allocation ids 2, 3, 4: the order of memories and the order
+    of allocation ids disagree).  Task A (box [6,12)) and then task B (box
+    [0,6)) write the buffer one_to_one, so every device holds one element
+    range of A and one of B.  Task C reads everything on every device."""
+    s = S.Stream(1, 3, 3, horizon_step=16, lookahead=0, name="group_order")
+    b = s.buffer(1, (12,), 4, S.INIT_HOST)
+    s.task(1, (0,), (2,), [S.Access(b, S.READ, S.FIXED, fixed_lo=(0, 0, 0), fixed_hi=(12, 1, 1))])
+    s.task(1, (0,), (12,), [S.Access(b, S.READ, S.ALL)])
+    s.task(1, (6,), (12,), [S.Access(b, S.WRITE, S.ONE_TO_ONE)])
+    s.task(1, (0,), (6,), [S.Access(b, S.WRITE, S.ONE_TO_ONE)])
+    s.task(1, (0,), (12,), [S.Access(b, S.READ, S.ALL)])
+    s.shutdown()
+    return s
+
+
+def check_group_order(out):
+    """Sec. 3.3 splits the stale part of a read by original producer and by
+    source allocation; the order of the resulting copies is the reading
+    "ascending (producer memory, producer, source allocation)".  Worked by
+    hand for group_order_stream: after A ([6,8) on M2, [8,10) on M3, [10,12)
+    on M4) and B ([0,2) on M2, [2,4) on M3, [4,6) on M4) -- A's kernels have
+    the smaller ids -- task C's chunk on M2 copies from M3 first (A's range,
+    then B's), then from M4; the chunk on M3 copies from M2 (allocation 4)
+    before M4 (allocation 3), so memory order, not allocation order, leads."""
+    ins = out["instructions"]
+    c_copies = [r for r in ins if int(r["kind"]) == COPY and int(r["task"]) == 4]
+    got = [(int(r["mem"]), int(r["src_mem"]), int(r["src_alloc"]), int(r["min"][0]), int(r["max"][0]))
+           for r in c_copies]
+    want = [(2, 3, 2, 8, 10), (2, 3, 2, 2, 4), (2, 4, 3, 10, 12), (2, 4, 3, 4, 6),
+            (3, 2, 4, 6, 8), (3, 2, 4, 0, 2), (3, 4, 3, 10, 12), (3, 4, 3, 4, 6),
+            (4, 2, 4, 6, 8), (4, 2, 4, 0, 2), (4, 3, 2, 8, 10), (4, 3, 2, 2, 4)]
+    assert got == want, got
+    kern = {(int(r["task"]), int(r["chunk"])): int(r["id"]) for r in ins if int(r["kind"]) == KERNEL}
+    producer = {(3, 8): kern[(2, 1)], (3, 2): kern[(3, 1)], (4, 10): kern[(2, 2)], (4, 4): kern[(3, 2)],
+                (2, 6): kern[(2, 0)], (2, 0): kern[(3, 0)]}
+    assert kern[(2, 0)] < kern[(2, 1)] < kern[(2, 2)] < kern[(3, 0)]
+    for r in c_copies:
+        p = producer[(int(r["src_mem"]), int(r["min"][0]))]
+        assert preds(out, int(r["id"])).get(p, 0) & DEP_TRUE
+
+
+def test_copy_group_order_hand_worked():
+    check_group_order(oracle.run_stream(group_order_stream()))

@@ -2,9 +2,10 @@
 
 Every stream here is tiny; `bruteforce.check_stream` executes the emitted
 graph element by element (sequential semantics, race freedom, coherence,
-allocation and front invariants) without restating the generation rules.
-The mutation tests plant plausible mistakes in a copy of the oracle's
-source (on the CPU) and require the brute-force checks to reject each one.
+allocation, resize and front invariants, exact edge sets, the command
+queue).  The mutation tests plant plausible mistakes in a copy of the
+oracle's source (on the CPU) and require a hand-worked pin or a brute-force
+check to reject each one.
 """
 import ctypes
 import os
@@ -105,7 +106,34 @@ MUTANTS = {
     "horizon_substitutes_readers_too_far": ("if (r < p) r = p;", "r = p;"),
     "uninit_not_tracked": ("for (const Box& p : subtract_all({rg.box}, bf.initialised)) bf.initialised.push_back(p);",
                            ";"),
+    # edges from map entries outside the accessed region
+    "edges_ignore_region": ("if (!intersects(e.box, a.box)) continue;", ";"),
+    # an OUTPUT edge from the writer even when readers take ANTI edges
+    "output_with_anti": ("} else {\n                        s.add(e.writer, is_alloc(e.writer) ? IGO_DEP_LIFETIME : "
+                         "IGO_DEP_OUTPUT);\n                    }",
+                         "}\n                    s.add(e.writer, is_alloc(e.writer) ? IGO_DEP_LIFETIME : "
+                         "IGO_DEP_OUTPUT);"),
+    # the allocating predicate ignores the plan of queued commands
+    "allocating_vs_live_only": ("std::vector<Box> v = (!queue.empty() && it != plan.end()) ? it->second : "
+                                "live_boxes(r.buffer, r.mem);",
+                                "std::vector<Box> v = live_boxes(r.buffer, r.mem);\n            (void)it;"),
+    # a resize copies the whole old allocation, up to date or not
+    "resize_copies_whole_box": ("if (e.mask.test(m)) {\n                            Box in",
+                                "if (true) {\n                            Box in"),
+    # copy groups in descending (producer memory, producer, source) order
+    "group_order_reversed": ("std::map<std::tuple<uint16_t, uint32_t, uint32_t>, std::vector<Box>> groups;",
+                             "std::map<std::tuple<uint16_t, uint32_t, uint32_t>, std::vector<Box>,\n"
+                             "                         std::greater<std::tuple<uint16_t, uint32_t, uint32_t>>> groups;"),
 }
+
+
+def _group_order_pin():
+    from test_oracle_scenarios import check_group_order, group_order_stream
+    check_group_order(oracle.run_stream(group_order_stream()))
+
+
+# hand-worked pins that are run against every mutant before the streams
+PIN_CASES = [_group_order_pin]
 
 def _overlap_stream():
     s = S.Stream(1, 2, 2, lookahead=0)
@@ -152,7 +180,13 @@ def test_mutant_is_caught(name, mutant_dir):
         oracle._lib = None
         oracle.LIB_PATH = so
         caught = False
-        for s in MUTANT_STREAMS:
+        for pin in PIN_CASES:
+            try:
+                pin()
+            except AssertionError:
+                caught = True
+                break
+        for s in [] if caught else MUTANT_STREAMS:
             try:
                 check_stream(s, oracle.run_stream(s), n_random_orders=0)
             except (Failure, IndexError, KeyError):
@@ -161,3 +195,37 @@ def test_mutant_is_caught(name, mutant_dir):
         assert caught, f"mutant {name} passed every brute-force check"
     finally:
         oracle._lib, oracle.LIB_PATH = saved_lib, saved_path
+
+
+@pytest.mark.parametrize("seed", range(0, 80, 4))
+def test_algorithmic_byte_terms(seed):
+    """The R17 counters equal what the records show: one writer update per
+    ALLOC, COPY and kernel write; one reader insertion per COPY and kernel
+    read; one buffer-map update per coherence COPY and kernel write; one
+    mapper box per non-empty chunk and accessor."""
+    from bruteforce import map_py, split_py, box_empty
+    s = S.random_small(seed) if seed % 8 else S.nbody(n=24, steps=4, nodes=2, devices=2, chunks=8)
+    out = oracle.run_stream(s)
+    ins, binds = out["instructions"], out["bindings"]
+    kind = ins["kind"]
+    n_alloc = int((kind == oracle.ALLOC).sum())
+    n_copy = int((kind == oracle.COPY).sum())
+    n_resize = int(((kind == oracle.COPY) & ((ins["flags"] & oracle.F_RESIZE) != 0)).sum())
+    tasks = [c[1] for c in s.cmds if c[0] == "task"]
+    kw = kr = 0
+    for b in binds:
+        if int(b["alloc"]) == 0:
+            continue
+        mode = tasks[int(ins[int(b["instr"])]["task"])].accesses[int(b["access"])].mode
+        kw += bool(mode & S.WRITE)
+        kr += bool(mode & S.READ)
+    boxes = 0
+    for t in tasks:
+        for ch in split_py(s.nodes, s.devices, s.chunks, t.lo, t.hi):
+            if not box_empty(ch):
+                boxes += len(t.accesses)
+    st = out["stats"]
+    assert st["u_w"] == n_alloc + n_copy + kw
+    assert st["u_r"] == n_copy + kr
+    assert st["u_b"] == n_copy - n_resize + kw
+    assert st["map_boxes"] == boxes
