@@ -90,6 +90,14 @@ def test_sim_random_streams(seed, sim_lib):
     assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), s.name)
 
 
+@pytest.mark.parametrize("seed", range(1, 60, 3))
+def test_sim_racy_random_streams(seed, sim_lib):
+    """Reads of regions other chunks of the same task write: reads see the
+    state before the task (the ordered kernel path)."""
+    s = S.random_small(seed, race_free=False)
+    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), s.name + "_racy")
+
+
 def test_sim_invalid_arguments(sim_lib):
     ctx = B.Context(1, 2, lib_path=sim_lib, threads=64)
     b = ctx.buffer_create(2, (8, 8, 1), 4, 1)

@@ -268,3 +268,39 @@ def test_windowed_batch_matches_oracle():
         assert ctx.sync() == 0
         assert_same(oracle.run_stream(s), ctx.fetch_all(), "replay:" + s.name)
     bt.close()
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_racy_random_streams(seed):
+    """Reads of regions that other chunks of the same task write (a user
+    race): reads see the state before the task, only overlapping writes are
+    errors.  Such tasks take the ordered kernel path."""
+    s = S.random_small(seed, race_free=False)
+    want, got = run_both(s)
+    assert_same(want, got, s.name + "_racy")
+
+
+# full-size streams of the batched workload with 512-1024 chunks and all or
+# slice reads over up to 128 devices (the workload's heaviest kind of task)
+BATCHED_FULL = [88, 91, 165, 138]
+
+
+def test_batched_full_size_streams_with_all_reads():
+    import json
+    import os
+    from paper_2503_10516_amd import batch as BT
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "batched_digests.json")))
+    rows = {r["index"]: r for r in gold["streams"]}
+    streams = [S.batched_stream(S.BATCHED_SEED, i, w_all=gold["w_all"], w_slice=gold["w_slice"])
+               for i in BATCHED_FULL]
+    for s in streams:
+        print(f"[gpu] batched full {s.name}: {s.n_tasks} tasks, {s.chunks} chunks, {s.nodes} nodes", flush=True)
+    bt = BT.Batch(streams, threads=256)
+    bt.size(window=400)
+    for i, ctx in zip(BATCHED_FULL, bt.contexts):
+        assert ctx.sync() == 0
+        st = ctx.stats()
+        for k in DIGESTS + ("per_kind", "per_dep"):
+            assert st[k] == rows[i][k], (i, k)
+    bt.close()
