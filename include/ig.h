@@ -297,6 +297,25 @@ typedef struct ig_progress {
 } ig_progress;
 ig_status ig_batch_progress(ig_context* const* ctxs, size_t n, void* stream, ig_progress* out);
 
+/* As ig_batch_progress, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The context-pointer table and the gathered progress words live
+ * in a fixed device array of IG_NOALLOC_SCRATCH_BYTES that every GPU holds
+ * once for the life of the process (its address is looked up per device on
+ * the first call with that device current), instead of the first context's
+ * staging area; the caller's `out` array doubles as the host staging of the
+ * table.  Calls nothing that allocates (no hipMalloc/hipFree, no host heap).
+ * Every word read back is written by the gather kernel of the same call, so
+ * nothing needs clearing between calls.  Calls that overlap on one GPU (from
+ * several threads or on several streams) share that array and race; the
+ * caller must order them.  Errors: IG_E_INVALID (as ig_batch_progress),
+ * IG_E_CAPACITY (n > IG_NOALLOC_MAX_CONTEXTS), IG_E_DEVICE (a HIP error, or
+ * a device index >= IG_NOALLOC_MAX_DEVICES). */
+#define IG_NOALLOC_MAX_CONTEXTS 4096
+#define IG_NOALLOC_MAX_DEVICES 64
+#define IG_NOALLOC_SCRATCH_BYTES (IG_NOALLOC_MAX_CONTEXTS * (8 + 32))
+ig_status ig_batch_progress_noalloc(ig_context* const* ctxs, size_t n, void* stream, ig_progress* out);
+
 /* A captured batched re-analysis (Sec. 3 graph generation for many streams
  * in one persistent launch): the commands recorded so far are uploaded once;
  * every ig_graph_launch forgets the previous results of all n contexts and

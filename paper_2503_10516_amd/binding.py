@@ -82,6 +82,7 @@ EXPORTS = [
     "ig_fetch_instructions", "ig_fetch_bindings", "ig_fetch_edges", "ig_fetch_task_status",
     "ig_fetch_task_times", "ig_stats_get", "ig_status_str", "ig_batch_rewind", "ig_batch_progress",
     "ig_batch_graph_create", "ig_graph_launch", "ig_graph_destroy", "ig_batch_flush_window",
+    "ig_batch_progress_noalloc",
 ]
 
 _libs: Dict[str, ctypes.CDLL] = {}
@@ -112,6 +113,7 @@ def lib(path: Optional[str] = None) -> ctypes.CDLL:
     L.ig_batch_flush_window.argtypes = [P(vp), ctypes.c_size_t, vp, ctypes.c_uint32]
     L.ig_batch_rewind.argtypes = [P(vp), ctypes.c_size_t, vp]
     L.ig_batch_progress.argtypes = [P(vp), ctypes.c_size_t, vp, vp]
+    L.ig_batch_progress_noalloc.argtypes = [P(vp), ctypes.c_size_t, vp, vp]
     L.ig_batch_graph_create.argtypes = [P(vp), ctypes.c_size_t, vp, P(vp)]
     L.ig_graph_launch.argtypes = [vp, vp]
     L.ig_graph_destroy.argtypes = [vp]
@@ -468,14 +470,16 @@ def batch_rewind(contexts: Sequence[Context], stream=None) -> None:
         raise IgError("ig_batch_rewind", st)
 
 
-def batch_progress(contexts: Sequence[Context], stream=None) -> np.ndarray:
+def batch_progress(contexts: Sequence[Context], stream=None, noalloc: bool = False) -> np.ndarray:
     """(n, 6) int64: tasks_done, tasks_seen, error, finished,
-    capacity_exceeded, commands_done per context."""
+    capacity_exceeded, commands_done per context.  noalloc: use
+    ig_batch_progress_noalloc (fixed device scratch, at most 4096 contexts)."""
     out = (Progress * len(contexts))()
-    st = contexts[0].L.ig_batch_progress(_ctx_array(contexts), len(contexts), _stream_ptr(stream),
-                                         ctypes.cast(out, ctypes.c_void_p))
+    name = "ig_batch_progress_noalloc" if noalloc else "ig_batch_progress"
+    st = getattr(contexts[0].L, name)(_ctx_array(contexts), len(contexts), _stream_ptr(stream),
+                                      ctypes.cast(out, ctypes.c_void_p))
     if st != 0:
-        raise IgError("ig_batch_progress", st)
+        raise IgError(name, st)
     return np.array([[p.tasks_done, p.tasks_seen, p.error, p.finished, p.capacity_exceeded, p.commands_done]
                      for p in out], dtype=np.int64)
 

@@ -550,6 +550,39 @@ ig_status ig_batch_progress(ig_context* const* ctxs, size_t n, void* stream, ig_
     return IG_OK;
 }
 
+static_assert(sizeof(ig_progress) == 32, "ig_progress doubles as 4 words of gather output");
+
+ig_status ig_batch_progress_noalloc(ig_context* const* ctxs, size_t n, void* stream, ig_progress* out) {
+    if (!out) return IG_E_INVALID;
+    ig_status st = check_batch(ctxs, n);
+    if (st != IG_OK) return st;
+    if (n > IG_NOALLOC_MAX_CONTEXTS) return IG_E_CAPACITY;
+    void* s = stream ? stream : ctxs[0]->stream;
+    void* scr = nullptr;
+    if (igrt::noalloc_scratch(&scr) != 0) return IG_E_DEVICE;
+    DevCtx** table = (DevCtx**)scr;
+    uint64_t* dev_out = (uint64_t*)((char*)scr + (size_t)IG_NOALLOC_MAX_CONTEXTS * sizeof(DevCtx*));
+    // the caller's array stages the pointer table (8 of its 32 bytes per context)
+    DevCtx** host_table = (DevCtx**)(void*)out;
+    for (size_t i = 0; i < n; ++i) host_table[i] = ctxs[i]->dctx;
+    if (igrt::copy_h2d(table, host_table, n * sizeof(DevCtx*), s) != 0) return IG_E_DEVICE;
+    if (igrt::stream_sync(s) != 0) return IG_E_DEVICE;  // the staging is overwritten below
+    if (igrt::launch_gather(table, (unsigned)n, dev_out, s) != 0) return IG_E_DEVICE;
+    if (igrt::copy_d2h(out, dev_out, 32 * n, s) != 0) return IG_E_DEVICE;
+    if (igrt::stream_sync(s) != 0) return IG_E_DEVICE;
+    for (size_t i = 0; i < n; ++i) {
+        u64 w[4];
+        std::memcpy(w, (const char*)out + 32 * i, sizeof w);
+        out[i].tasks_done = w[0] & 0xFFFFFFFFu;
+        out[i].tasks_seen = w[0] >> 32;
+        out[i].error = (int32_t)(uint32_t)(w[1] & 0xFFFFFFFFu);
+        out[i].capacity_exceeded = (uint32_t)(w[1] >> 32);
+        out[i].finished = (uint32_t)w[2];
+        out[i].commands_done = (uint32_t)w[3];
+    }
+    return IG_OK;
+}
+
 struct ig_graph {
     std::vector<ig_context*> ctxs;
     void* table = nullptr;  // device copy of the context pointers (graph-owned)

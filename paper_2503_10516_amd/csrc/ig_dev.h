@@ -346,5 +346,8 @@ int launch_pack_bindings(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n,
 int launch_pack_edges(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_edge* out_dev, void* stream);
 int launch_stats(const igd::DevCtx* dev_ctx, uint64_t n_instr, uint64_t n_bind, uint64_t n_edge,
                  igd::DevStats* out_dev, void* stream);
+// Device address of this GPU's fixed scratch array (IG_NOALLOC_SCRATCH_BYTES),
+// looked up once per device on first use; never allocates.
+int noalloc_scratch(void** out);
 const char* last_error();
 }  // namespace igrt

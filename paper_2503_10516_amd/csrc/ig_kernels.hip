@@ -17,6 +17,8 @@
 // 3.5 (horizons/epochs), Table 1 (instruction kinds), the dependency-kind
 // legend of the IDAG figure (Sec. 3.6), Sec. 4.1 (topological emission),
 // Sec. 4.3 (lookahead), Sec. 4.4 (debug checks).
+#include <mutex>
+
 #include "ig_dev.h"
 
 namespace igd {
@@ -3086,6 +3088,14 @@ __global__ void __launch_bounds__(256) ig_stats_kernel(const DevCtx* c, u64 ni, 
     }
 }
 
+// Fixed device memory of the entry points that allocate nothing
+// (ig_batch_progress_noalloc): a context-pointer table followed by the
+// gathered progress words.  Every GPU holds its own copy until the process
+// ends.  Host code must never pass this name to a kernel or a copy (on the
+// host it is only a stand-in): it uses the device address that
+// igrt::noalloc_scratch looks up per device.
+static __device__ __align__(256) unsigned char scratch[IG_NOALLOC_SCRATCH_BYTES];
+
 namespace igrt {
 static thread_local char g_err[256];
 static int check(hipError_t e) {
@@ -3160,6 +3170,28 @@ int graph_launch(void* exec, void* stream) {
     return check(hipGraphLaunch((hipGraphExec_t)exec, (hipStream_t)stream));
 }
 int graph_destroy(void* exec) { return check(hipGraphExecDestroy((hipGraphExec_t)exec)); }
+// The address of `scratch` on the current device, looked up on the first call
+// made with that device current and kept per device (each GPU has its own
+// copy of the array at its own address).
+int noalloc_scratch(void** out) {
+    static std::mutex mu;
+    static void* addr[IG_NOALLOC_MAX_DEVICES];
+    int dev = -1;
+    if (check(hipGetDevice(&dev))) return -1;
+    if (dev < 0 || dev >= IG_NOALLOC_MAX_DEVICES) {
+        snprintf(g_err, sizeof g_err, "device %d beyond the %d devices the scratch table covers", dev,
+                 IG_NOALLOC_MAX_DEVICES);
+        return -1;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        if (check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)))) return -1;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return 0;
+}
 int launch_pack_instructions(const DevCtx* c, uint64_t first, uint64_t n, ig_instruction* out, void* stream) {
     if (!n) return 0;
     hipLaunchKernelGGL(ig_pack_instructions, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, c, first, n, out);

@@ -110,6 +110,12 @@ int launch_gather(DevCtx* const* ptrs, unsigned n, uint64_t* out, void*) {
     for (unsigned i = 0; i < n; ++i) gather_progress(*ptrs[i], (u64*)out + 4 * (size_t)i);
     return 0;
 }
+// The emulation's stand-in for the fixed device array of the no-alloc calls.
+alignas(256) static unsigned char g_noalloc_scratch[IG_NOALLOC_SCRATCH_BYTES];
+int noalloc_scratch(void** out) {
+    *out = g_noalloc_scratch;
+    return 0;
+}
 // A "graph" of the emulation: the recorded launch sequence, replayed.
 struct SimGraph {
     std::vector<DevCtx*> ptrs;

@@ -6,6 +6,7 @@
   workgroup emulated by threads and barriers (a test-only build, never used
   by the product), reproduces the oracle bit for bit on small streams.
 """
+import ctypes
 import os
 import re
 import subprocess
@@ -251,3 +252,28 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run(["python3", os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "exactly one GPU" in r.stdout
+
+
+def test_sim_progress_noalloc_equals_progress(sim_lib):
+    """ig_batch_progress_noalloc (fixed scratch) reports what
+    ig_batch_progress reports, on two calls in a row, the second over fewer
+    contexts; more than its maximum is refused."""
+    streams = [S.stencil_1d(n=256, tasks=17), S.nbody_example(), S.random_small(3), S.growing(width=12, steps=6,
+                                                                                             devices=4)]
+    ctxs = []
+    for s in streams:
+        ctx = B.make_context(s, lib_path=sim_lib, threads=64)
+        ctx.record(S.Stream(s.nodes, s.devices, s.chunks, cmds=s.cmds[: len(s.cmds) // 2]))
+        ctxs.append(ctx)
+    B.batch_flush(ctxs)
+    for sub in (ctxs, ctxs[1:3]):
+        want = B.batch_progress(sub)
+        got = B.batch_progress(sub, noalloc=True)
+        assert want.shape == got.shape == (len(sub), 6)
+        assert (want == got).all(), (want, got)
+    too_many = (ctypes.c_void_p * 4097)(*([ctxs[0].h] * 4097))
+    out = (B.Progress * 4097)()
+    assert ctxs[0].L.ig_batch_progress_noalloc(too_many, 4097, None, ctypes.cast(out, ctypes.c_void_p)) == \
+        B.IG_E_CAPACITY
+    for c in ctxs:
+        c.close()
