@@ -143,6 +143,9 @@ static u64 carve(const Caps& k, char* base, DevCtx* h, Tail* tail = nullptr) {
     TAKE(cons_cnt, u32, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
     TAKE(cons_x, u32, (u64)MAX_CHUNKS * IG_MAX_ACCESS);
     TAKE(k_rank, u32, (u64)MAX_CHUNKS);
+    TAKE(big_n, u32, k.n_mem);
+    TAKE(big_idx, u32, (u64)k.n_mem * MAX_BIG);
+    TAKE(tm, u32, 4ull * k.n_mem);
     TAKE(copies, CopyRec, k.cap_unit);
     TAKE(dev_cnt, u32, k.n_dev);
     TAKE(dev_base, u32, k.n_dev);

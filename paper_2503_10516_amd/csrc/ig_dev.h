@@ -67,6 +67,12 @@ inline unsigned long long atomicOr(unsigned long long* p, unsigned long long v) 
 }
 inline unsigned atomicOr(unsigned* p, unsigned v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
 inline unsigned atomicExch(unsigned* p, unsigned v) { return __atomic_exchange_n(p, v, __ATOMIC_SEQ_CST); }
+inline unsigned atomicMax(unsigned* p, unsigned v) {
+    unsigned cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (cur < v && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+    }
+    return cur;
+}
 inline unsigned atomicCAS(unsigned* p, unsigned cmp, unsigned v) {
     __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
     return cmp;
@@ -75,6 +81,8 @@ inline unsigned long long atomicCAS(unsigned long long* p, unsigned long long cm
     __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
     return cmp;
 }
+inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
+inline int __ffsll(long long v) { return __builtin_ffsll(v); }
 inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 inline void __threadfence_block() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 unsigned long long ig_clock();
@@ -120,6 +128,8 @@ constexpr u32 MAX_THREADS = 1024;
 constexpr u32 MAX_CHUNKS = 4096;
 constexpr u32 RB_SLOTS = 7;    // reader ids per reader block (+1 word: next)
 constexpr u32 RD_CACHE = 4;    // accesses per kernel whose read scans can be shared
+constexpr u32 MAX_BIG = 4;     // large coherence reads per memory and task scanned by a thread team
+constexpr u32 BIG_CELLS = 512; // grid cells from which a read region is scanned by a team
 
 enum CmdKind : u32 { CMD_BUFFER = 1, CMD_TASK = 2, CMD_EPOCH = 3, CMD_DESTROY = 4, CMD_SHUTDOWN = 5 };
 
@@ -275,6 +285,9 @@ struct DevCtx {
     u32* cons_cnt;        // [MAX_CHUNKS * IG_MAX_ACCESS]
     u32* cons_x;          // [MAX_CHUNKS * IG_MAX_ACCESS] first copy of (chunk, access) within its device
     u32* k_rank;          // [MAX_CHUNKS] kernel index of a chunk within its device (NONE: empty)
+    u32* big_n;           // [n_mem] large coherence reads deferred to the team scan
+    u32* big_idx;         // [n_mem * MAX_BIG] their (chunk * IG_MAX_ACCESS + access)
+    u32* tm;              // [n_mem * 4] words a thread team shares (offsets, totals, flags)
     CopyRec* copies;      // [cap_unit]
     u32* dev_cnt;         // [n_dev] copies per device, then kernels per device
     u32* dev_base;        // [n_dev]

@@ -42,6 +42,7 @@ struct Shared {
     u32 t_stamps;  // some write may leave its chunk's dim-0 range: check overlaps cell by cell
     u64 t_wbufs;   // buffers the task writes (bit per buffer)
     u32 t_par;     // kernels may be emitted in parallel (see kernels_emit_par)
+    u32 t_gmask;   // with t_par: accesses read through one shared source list per device
     i64 t_lo[3], t_hi[3];
     u32 n_alloc_instr, n_new_allocs, n_copies, n_kernels;
     u32 win_first, win_n;  // lookahead window (queue positions)
@@ -1810,11 +1811,23 @@ IGD u32 emit_groups(DevCtx& c, Shared& sh, const u64* key, const u32* val, u32 n
 // ===========================================================================
 constexpr u32 REG_NEED = 16;
 
+// Thread teams: with several threads per simulated device, the G threads of a
+// team (consecutive, within one wave) share one memory's large scans.  G is
+// the largest power of two (at most 64) with G * n_dev <= threads; memories
+// are taken in passes of threads / G.
+IGD u32 team_size(const DevCtx& c) {
+    u32 g = 1;
+    while (g < 64 && 2 * g * c.n_dev <= nt()) g <<= 1;
+    return g;
+}
+
 IGN void coherence_count(DevCtx& c, Shared& sh) {
     const u32 A = sh.t_nacc, K = c.per_dev;
+    const u32 G = team_size(c);
     for (u32 m = tid(); m < c.n_mem; m += nt()) {
         if (m < 2) continue;
         const u32 d = m - 2;
+        u32 nbig = 0;  // large reads of this memory deferred to coherence_big
         IG_SIM_CHECK(tid() < c.n_workers, "coherence scratch per worker");
         u64* key = c.wk_key + (size_t)tid() * c.cap_scr;
         u32* val = c.wk_val + (size_t)tid() * c.cap_scr;
@@ -1856,6 +1869,45 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                     seen[0][t] = key7[t];
                 }
                 n_seen = n_seen < 2 ? n_seen + 1 : 2;
+                // A large read deferred to the team scan makes its cells up
+                // to date there, after this loop; a later read of the same
+                // buffer must find them covered already (the consumer split
+                // in (chunk, access) order), so it skips them here, or is
+                // skipped whole when the deferred region contains it.
+                u32 nex = 0;
+                u32 exlo[MAX_BIG][3], exhi[MAX_BIG][3];
+                bool inside = false;
+#pragma unroll
+                for (u32 q = 0; q < MAX_BIG; ++q) {
+                    if (q >= nbig) break;
+                    const Region& D = c.reg[c.big_idx[m * MAX_BIG + q]];
+                    if (D.buffer != b) continue;
+                    bool cont = true, meet = true;
+#pragma unroll
+                    for (u32 t3 = 0; t3 < 3; ++t3) {
+                        cont = cont && D.clo[t3] <= r.clo[t3] && r.chi[t3] <= D.chi[t3];
+                        meet = meet && D.clo[t3] < r.chi[t3] && r.clo[t3] < D.chi[t3];
+                    }
+                    inside = inside || cont;
+                    if (!cont && meet) {
+#pragma unroll
+                        for (u32 e = 0; e < MAX_BIG; ++e)
+                            if (e == nex)
+#pragma unroll
+                                for (u32 t3 = 0; t3 < 3; ++t3) {
+                                    exlo[e][t3] = D.clo[t3];
+                                    exhi[e][t3] = D.chi[t3];
+                                }
+                        ++nex;
+                    }
+                }
+                if (inside) continue;
+                const u32 ncr = (r.chi[0] - r.clo[0]) * (r.chi[1] - r.clo[1]) * (r.chi[2] - r.clo[2]);
+                if (G > 1 && ncr >= BIG_CELLS && nbig < MAX_BIG) {
+                    c.big_idx[m * MAX_BIG + nbig] = idx;
+                    ++nbig;
+                    continue;
+                }
                 const DBuf& B = c.bufs[b];
                 const u32* prod = W32(c, B.prod_off);
                 const u32* pmv = W32(c, B.pm_off);
@@ -1871,6 +1923,14 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                 for (u32 i0 = r.clo[0]; i0 < r.chi[0]; ++i0)
                     for (u32 i1 = r.clo[1]; i1 < r.chi[1]; ++i1)
                         for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2) {
+                            if (nex) {
+                                bool ex = false;
+#pragma unroll
+                                for (u32 e = 0; e < MAX_BIG; ++e)
+                                    ex = ex || (e < nex && i0 >= exlo[e][0] && i0 < exhi[e][0] && i1 >= exlo[e][1] &&
+                                                i1 < exhi[e][1] && i2 >= exlo[e][2] && i2 < exhi[e][2]);
+                                if (ex) continue;
+                            }
                             const u32 cell = cell_of(B, i0, i1, i2);
                             const u64* mk = mask + (size_t)cell * c.mw;
                             if ((mk[m >> 6] >> (m & 63)) & 1) continue;
@@ -1974,6 +2034,173 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
         }
         c.dev_cnt[d] = total;
         c.kdev_cnt[d] = kcount;
+        c.big_n[m] = nbig;
+    }
+}
+
+// The key of a stale cell (producer memory, original producer, source
+// allocation), as in coherence_count; 0 with an error when no live
+// allocation on the producer memory holds the cell.
+struct SrcCache {
+    u32 pm, src, lo[3], hi[3];
+};
+
+IGD u64 stale_key(DevCtx& c, Shared& sh, SrcCache& l, u32 b, u32 pm, u32 p, u32 i0, u32 i1, u32 i2) {
+    if (!(pm == l.pm && i0 >= l.lo[0] && i0 < l.hi[0] && i1 >= l.lo[1] && i1 < l.hi[1] && i2 >= l.lo[2] &&
+          i2 < l.hi[2])) {
+        const u32 src = live_containing_cell(c, b, pm, i0, i1, i2);
+        if (src == 0) {
+            set_error(sh, IG_E_DEVICE);
+            return 0;
+        }
+        const DAlloc& sa = c.allocs[src];
+        l.pm = pm;
+        l.src = src;
+        for (u32 t3 = 0; t3 < 3; ++t3) {
+            l.lo[t3] = sa.clo[t3];
+            l.hi[t3] = sa.chi[t3];
+        }
+    }
+    return ((u64)pm << 56) | ((u64)p << 24) | (u64)(l.src & 0xFFFFFF);
+}
+
+// Large reads deferred by coherence_count, scanned by the team of their
+// memory: round r takes every memory's r-th deferred read (in (chunk, access)
+// order), so each sees the up-to-date state its predecessors left.
+//  1. each member scans a contiguous part of the region's cells (cell order)
+//     and keeps its stale cells' (key, cell) pairs;
+//  2. the parts are concatenated in member order (block scan), which is the
+//     cell order of one sequential scan, and sorted stably by key if needed;
+//  3. members take contiguous parts of the list, emit the groups that start
+//     in their part (canonical boxes, block scan of the counts for the copy
+//     slots) and mark the copied cells up to date.
+IGN void coherence_big(DevCtx& c, Shared& sh) {
+    if (tid() == 0) sh.flag = 0;
+    bar();
+    for (u32 m = tid() + 2; m < c.n_mem; m += nt()) atomicMax(&sh.flag, c.big_n[m]);
+    const u32 rounds = uniform(sh.flag);
+    if (rounds == 0) return;
+    const u32 G = team_size(c), TP = nt() / G, ts = tid() / G, g = tid() % G;
+    const u32 seg = c.cap_scr / G;
+    for (u32 rnd = 0; rnd < rounds; ++rnd) {
+        for (u32 base = 0; base < c.n_dev; base += TP) {
+            const u32 d = base + ts, m = d + 2;
+            const bool act = d < c.n_dev && rnd < c.big_n[m];
+            const u32 w = m % nt();  // the memory's worker: its scratch arrays
+            IG_SIM_CHECK(!act || w < c.n_workers, "team scratch per worker");
+            u64* key = c.wk_key + (size_t)w * c.cap_scr;
+            u32* val = c.wk_val + (size_t)w * c.cap_scr;
+            u64* key2 = c.wk_key2 + (size_t)w * c.cap_scr;
+            u32* val2 = c.wk_val2 + (size_t)w * c.cap_scr;
+            u32* tm = c.tm + 4 * (size_t)m;
+            u32 idx = 0, k = 0, j = 0, b = 0, n_g = 0;
+            bool ordered = true;
+            Region r;
+            if (act) {
+                idx = c.big_idx[m * MAX_BIG + rnd];
+                k = idx / IG_MAX_ACCESS;
+                j = idx % IG_MAX_ACCESS;
+                r = c.reg[idx];
+                b = r.buffer;
+                if (g == 0) tm[2] = 0;
+                const u32 n1 = r.chi[1] - r.clo[1], n2 = r.chi[2] - r.clo[2];
+                const u32 total = (r.chi[0] - r.clo[0]) * n1 * n2;
+                if (total > G * seg) cap_error(sh, IG_CAP_SCRATCH);
+                const u32 per = (total + G - 1) / G;
+                const u32 q0 = g * per < total ? g * per : total;
+                const u32 q1 = q0 + per < total ? q0 + per : total;
+                const DBuf& B = c.bufs[b];
+                const u32* prod = W32(c, B.prod_off);
+                const u32* pmv = W32(c, B.pm_off);
+                const u64* mask = W64(c, B.mask_off);
+                u64* mk_out = key + (size_t)g * seg;
+                u32* mv_out = val + (size_t)g * seg;
+                SrcCache l;
+                l.pm = NONE;
+                u64 last = 0;
+                u32 i2 = q0 % n2, i1 = (q0 / n2) % n1, i0 = q0 / (n1 * n2);
+                for (u32 q = q0; q < q1 && !sh.s.error; ++q) {
+                    const u32 a0 = r.clo[0] + i0, a1 = r.clo[1] + i1, a2 = r.clo[2] + i2;
+                    if (++i2 == n2) {
+                        i2 = 0;
+                        if (++i1 == n1) {
+                            i1 = 0;
+                            ++i0;
+                        }
+                    }
+                    const u32 cell = cell_of(B, a0, a1, a2);
+                    const u64* mk = mask + (size_t)cell * c.mw;
+                    if ((mk[m >> 6] >> (m & 63)) & 1) continue;
+                    u64 any = 0;
+                    for (u32 x = 0; x < c.mw; ++x) any |= mk[x];
+                    if (!any) continue;
+                    const u64 x = stale_key(c, sh, l, b, pmv[cell], eff_w(sh, prod[cell]), a0, a1, a2);
+                    if (x < last) ordered = false;
+                    last = x;
+                    mk_out[n_g] = x;
+                    mv_out[n_g] = cell;
+                    ++n_g;
+                }
+            }
+            u32 tot;
+            const u32 excl = block_excl(sh, act ? n_g : 0, &tot);
+            if (act && g == 0) tm[0] = excl;
+            bar();
+            const u32 off = act ? excl - tm[0] : 0;
+            if (act) {
+                if (g == G - 1) tm[1] = off + n_g;
+                if (!ordered) atomicOr(&tm[2], 1u);
+                for (u32 i = 0; i < n_g; ++i) {
+                    key2[off + i] = key[(size_t)g * seg + i];
+                    val2[off + i] = val[(size_t)g * seg + i];
+                }
+            }
+            bar();
+            const u32 n = act ? tm[1] : 0;
+            if (act && g > 0 && n_g > 0 && off > 0 && key2[off - 1] > key2[off]) atomicOr(&tm[2], 1u);
+            bar();
+            if (act && g == 0 && tm[2] && n > 1 && !sh.s.error) msort_kv(key2, val2, key, val, n);
+            if (failed(sh)) return;
+            // groups starting in this member's part of the list
+            u32 gs = 0, ge = 0, cnt = 0, dst = 0;
+            if (act && n > 0) {
+                const u32 per = (n + G - 1) / G;
+                const u32 e0 = g * per < n ? g * per : n, e1 = e0 + per < n ? e0 + per : n;
+                gs = e0;
+                while (gs < e1 && gs > 0 && key2[gs] == key2[gs - 1]) ++gs;
+                ge = gs;
+                if (gs < e1) {
+                    ge = e1;
+                    while (ge < n && key2[ge] == key2[ge - 1]) ++ge;
+                }
+                dst = live_containing(c, b, m, r.lo, r.hi);
+                if (dst == 0) set_error(sh, IG_E_DEVICE);
+                cnt = emit_groups(c, sh, key2 + gs, val2 + gs, ge - gs, c.bufs[b], k, j, b, dst, m, 0, false);
+            }
+            const u32 excl2 = block_excl(sh, act ? cnt : 0, &tot);
+            if (act && g == 0) tm[0] = excl2;
+            bar();
+            const u32 boff = act ? excl2 - tm[0] : 0;
+            if (act && g == G - 1) tm[1] = boff + cnt;
+            bar();
+            if (act && g == 0) {
+                const u32 all = tm[1];
+                const u32 at = atomicAdd(&sh.copy_top, all);
+                if (at + all > c.cap_unit) cap_error(sh, IG_CAP_UNIT);
+                tm[3] = at;
+                c.cons_off[idx] = at;
+                c.cons_cnt[idx] = all;
+                c.dev_cnt[d] += all;
+            }
+            if (failed(sh)) return;
+            if (act && ge > gs) {
+                const DBuf& B = c.bufs[b];
+                emit_groups(c, sh, key2 + gs, val2 + gs, ge - gs, B, k, j, b, dst, m, tm[3] + boff, true);
+                u64* mask = W64(c, B.mask_off);
+                for (u32 e = gs; e < ge; ++e) atomicOr(&mask[(size_t)val2[e] * c.mw + (m >> 6)], 1ull << (m & 63));
+            }
+            bar();
+        }
     }
 }
 
@@ -2202,8 +2429,15 @@ IGN void kernels_emit_seq(DevCtx& c, Shared& sh, u32 kern_first) {
 //  1. any thread takes any kernel: record, bindings, edges, writes;
 //  2. reader additions, split by cell among the threads of each device, in
 //     kernel order per cell (a cell the kernel itself wrote gets no reader).
+// The shared source list of grouped access j on device d (t_gmask): in the
+// worker scratch of the device's memory; its length in c.tm.
+IGD u64* group_list(DevCtx& c, u32 m, u32 j) {
+    return c.wk_rsrc + ((size_t)(m % nt()) * RD_CACHE + j) * c.cap_src;
+}
+
 IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
     const u32 A = sh.t_nacc, K = c.per_dev, C = c.chunks;
+    const u32 gmask = sh.t_gmask;
     // kernel rank of each chunk within its device (empty chunks have none)
     for (u32 d = tid(); d < c.n_dev; d += nt()) {
         u32 r = 0;
@@ -2212,6 +2446,42 @@ IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
             chunk_range(c, sh.t_lo[0], sh.t_hi[0], k, k0, k1);
             const bool empty = k0 >= k1 || sh.t_lo[1] >= sh.t_hi[1] || sh.t_lo[2] >= sh.t_hi[2];
             c.k_rank[k] = empty ? NONE : r++;
+        }
+    }
+    // grouped reads: one scan of the shared region per (device, access),
+    // sources sorted and de-duplicated once for all kernels of the device
+    if (gmask) {
+        for (u32 w = tid(); w < c.n_dev * RD_CACHE; w += nt()) {
+            const u32 d = w / RD_CACHE, j = w % RD_CACHE, m = d + 2;
+            if (!((gmask >> j) & 1)) continue;
+            IG_SIM_CHECK(m % nt() < c.n_workers, "group lists per worker");
+            c.tm[4 * m + j] = 0;
+            if (c.kdev_cnt[d] == 0) continue;  // no kernel on the device
+            const Region& rg = c.reg[(d * K) * IG_MAX_ACCESS + j];
+            u32 kk = d * K;  // the first chunk of the device with a region
+            while (kk < (d + 1) * K && c.reg[kk * IG_MAX_ACCESS + j].empty) ++kk;
+            if (kk == (d + 1) * K) continue;
+            const Region& rk = kk == d * K ? rg : c.reg[kk * IG_MAX_ACCESS + j];
+            const u32 al = live_containing(c, rk.buffer, m, rk.lo, rk.hi);
+            if (!al) {
+                set_error(sh, IG_E_DEVICE);
+                continue;
+            }
+            const DAlloc& a = c.allocs[al];
+            u64* src = group_list(c, m, j);
+            SrcSet t;
+            ss_init_buf(t, src, c.wk_src2 + (size_t)tid() * c.cap_src, c.cap_src);
+            scan_cells(am_cells(c, a), a, rk.clo, rk.chi, [&](const AmCell& e, AmCell*) { cell_read_edge(sh, t, e); });
+            u32 ns;
+            if (!t.spilled) {
+#pragma unroll
+                for (u32 i = 0; i < REG_SRC; ++i)
+                    if (i < t.n) src[i] = t.r[i];
+                ns = t.n;
+            } else {
+                ns = src_dedup(src, t.g.aux, t.g.n);
+            }
+            c.tm[4 * m + j] = ns;
         }
     }
     bar();
@@ -2241,8 +2511,21 @@ IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
         }
         SrcSet s;
         ss_init(c, s);
+        const u64* glist = nullptr;  // the first grouped access's list, merged at staging
+        u32 nglist = 0;
         for (u32 j = 0; j < A; ++j) {
             if (!al[j]) continue;
+            if ((gmask >> j) & 1) {
+                const u64* gl = group_list(c, m, j);
+                const u32 ng = c.tm[4 * m + j];
+                if (!glist) {
+                    glist = gl;
+                    nglist = ng;
+                } else {
+                    for (u32 i = 0; i < ng; ++i) ss_add(sh, s, (u32)(gl[i] >> 8), (u32)(gl[i] & 0xFF));
+                }
+                continue;
+            }
             const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
             const DAlloc& a = c.allocs[al[j]];
             const u32 mode = rg.mode;
@@ -2251,7 +2534,7 @@ IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
                 if (mode & IG_WRITE) cell_write_edge(c, sh, s, e);
             });
         }
-        stage(c, sh, x, s);
+        stage_with_list(c, sh, x, s, glist, nglist);
         for (u32 j = 0; j < A; ++j) {
             const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
             if (!al[j] || !(rg.mode & IG_WRITE)) continue;
@@ -2284,13 +2567,40 @@ IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
     for (u32 d = d0; d < nd; d += dstep) {
         if (nt() >= nd && d != d0) break;
         const u32 m = d + 2;
+        // grouped reads: the device's kernels as one run of reader ids on
+        // every cell of the shared region
+        if (gmask && c.kdev_cnt[d]) {
+            const u32 first = kern_first + c.kdev_base[d], nk = c.kdev_cnt[d];
+            for (u32 j = 0; j < RD_CACHE; ++j) {
+                if (!((gmask >> j) & 1)) continue;
+                u32 kk = d * K;
+                while (kk < (d + 1) * K && (c.k_rank[kk] == NONE || c.reg[kk * IG_MAX_ACCESS + j].empty)) ++kk;
+                if (kk == (d + 1) * K) continue;
+                const Region& rg = c.reg[kk * IG_MAX_ACCESS + j];
+                const u32 al = live_containing(c, rg.buffer, m, rg.lo, rg.hi);
+                if (!al) continue;
+                const DAlloc& a = c.allocs[al];
+                AmCell* cl = am_cells(c, a);
+                const u32 n1 = rg.chi[1] - rg.clo[1], n2 = rg.chi[2] - rg.clo[2];
+                const u32 total = (rg.chi[0] - rg.clo[0]) * n1 * n2;
+                for (u32 q = 0; q < total; ++q) {
+                    const u32 i2 = q % n2, i1 = (q / n2) % n1, i0 = q / (n1 * n2);
+                    const u32 l = alloc_local(a, rg.clo[0] + i0, rg.clo[1] + i1, rg.clo[2] + i2);
+                    if (l % G != g) continue;
+                    if (nk == 1)
+                        cell_add_reader_at(c, sh, m, cl + l, am_load(cl + l), first);
+                    else
+                        rd_append_range(c, sh, m, &cl[l].ov, first, nk);
+                }
+            }
+        }
         for (u32 k = d * K; k < (d + 1) * K; ++k) {
             const u32 rk = c.k_rank[k];
             if (rk == NONE) continue;
             const u32 x = kern_first + c.kdev_base[d] + rk;
             for (u32 j = 0; j < A; ++j) {
                 const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
-                if (rg.empty || !(rg.mode & IG_READ)) continue;
+                if (rg.empty || !(rg.mode & IG_READ) || ((gmask >> j) & 1)) continue;
                 const u32 al = live_containing(c, rg.buffer, m, rg.lo, rg.hi);
                 if (!al) continue;
                 const DAlloc& a = c.allocs[al];
@@ -2349,7 +2659,12 @@ IGN void load_task(DevCtx& c, Shared& sh, u32 ci) {
         // parallel kernel emission: every access to a written buffer stays in
         // its chunk's dim-0 range, and no pure read covers a region shared by
         // the chunks of a device (those share one scan in the ordered path)
-        u32 par = 1;
+        // A pure read of a buffer the task does not write through all,
+        // fixed or slice(0) has the same region in every chunk; its cells
+        // keep their writers through the task, so all kernels of a device
+        // share one list of its sources (t_gmask), and the kernels stay
+        // independent.  Beyond RD_CACHE such accesses use the ordered path.
+        u32 par = 1, gmask = 0;
         for (u32 j = 0; j < cmd.task.n_access; ++j) {
             const ig_access& a = cmd.task.access[j];
             const bool confined = a.mapper == IG_MAP_ONE_TO_ONE || (a.mapper == IG_MAP_SLICE && a.slice_dim != 0) ||
@@ -2357,9 +2672,15 @@ IGN void load_task(DevCtx& c, Shared& sh, u32 ci) {
             const bool allish = a.mapper == IG_MAP_ALL || a.mapper == IG_MAP_FIXED ||
                                 (a.mapper == IG_MAP_SLICE && a.slice_dim == 0);
             if (((wb >> a.buffer) & 1) && !confined) par = 0;
-            if (a.mode == IG_READ && !((wb >> a.buffer) & 1) && allish) par = 0;
+            if (a.mode == IG_READ && !((wb >> a.buffer) & 1) && allish) {
+                if (j < RD_CACHE)
+                    gmask |= 1u << j;
+                else
+                    par = 0;
+            }
         }
         sh.t_par = par;
+        sh.t_gmask = par ? gmask : 0;
     }
     bar();
 }
@@ -2399,6 +2720,8 @@ IGN void compile_task(DevCtx& c, Shared& sh, u32 ci, bool fresh) {
     for (u32 i = tid(); i < c.n_mem; i += nt()) c.inbox_cnt[i] = 0;
     bar();
     coherence_count(c, sh);
+    if (failed(sh)) return;
+    coherence_big(c, sh);
     if (failed(sh)) return;
     tick(c, sh, PH_COH_COUNT);
     // scans: copies and kernels per device, inbox slots per memory
@@ -2755,14 +3078,142 @@ IGN void create_buffer(DevCtx& c, Shared& sh, const DevCmd& cmd) {
 }
 
 // Sec. 3.2: a destroyed buffer's device allocations are freed (ascending id)
+// The FREE x of allocation a (Sec. 3.2), its edges found by the team of its
+// memory: every writer and reader of the allocation, after substitution,
+// lies in [S, x), so the members mark them in a bitmap of that range (one
+// part of the cells each) and the set bits, in order, are the sorted,
+// duplicate-free LIFETIME sources.  A range beyond the bitmap's size takes
+// the member-0 path with a sorted source list.
+IGN void team_free(DevCtx& c, Shared& sh, bool act, u32 m, u32 g, u32 G, u32 ai, u32 x) {
+    const u32 S = sh.s.S, E = sh.s.E;
+    const u32 R = act ? x - S : 0;
+    const u32 w = m % nt();
+    IG_SIM_CHECK(!act || w < c.n_workers, "free bitmap per worker");
+    u64* bm = c.wk_key + (size_t)w * c.cap_scr;
+    u32* tm = c.tm + 4 * (size_t)m;
+    const bool bits = act && (u64)R <= 64ull * c.cap_scr;
+    const DAlloc& a = c.allocs[act ? ai : 0];
+    const u32 words = (R + 63) / 64;
+    if (act && g == 0) put_instr(c, x, IG_FREE, 0, NONE, NONE, a.buffer, m, 0xFFFF, ai, 0, a.lo, a.hi);
+    if (act && !bits && g == 0) {
+        SrcSet s;
+        ss_init(c, s);
+        free_edges(c, sh, s, a);
+        stage(c, sh, x, s);
+    }
+    if (bits)
+        for (u32 i = g; i < words; i += G) bm[i] = 0;
+    bar();
+    const u32 per = act ? (a.ncells + G - 1) / G : 0;
+    const u32 l0 = act && g * per < a.ncells ? g * per : (act ? a.ncells : 0);
+    const u32 l1 = act && l0 + per < a.ncells ? l0 + per : (act ? a.ncells : 0);
+    if (bits) {
+        const AmCell* cl = am_cells(c, a);
+        auto mark = [&](u32 id) {
+            const u32 o = id - S;
+            if (o >= R) {
+                set_error(sh, IG_E_DEVICE);
+                return;
+            }
+            atomicOr(&bm[o >> 6], 1ull << (o & 63));
+        };
+        for (u32 l = l0; l < l1; ++l) {
+            const AmCell e = am_load(cl + l);
+            const u32 wr = e.w & ~W_ALLOC;
+            mark(wr < S ? S : wr);
+            u32 r;
+            if (e.r0 != NONE && eff_r(sh, e.r0, r)) mark(r);
+            if (e.r1 != NONE && eff_r(sh, e.r1, r)) mark(r);
+            rd_each(c, e.ov, [&](u32 first, u32 n) {
+                const u32 end = first + n;
+                u32 lo = first < E ? E : first;
+                if (lo >= end) return;
+                if (lo < S) {
+                    mark(S);
+                    lo = S;
+                }
+                if (lo >= end) return;  // the whole run reads as S
+                if (end - S > R) {
+                    set_error(sh, IG_E_DEVICE);
+                    return;
+                }
+                // bits [lo - S, end - S), word by word
+                for (u32 o = lo - S; o < end - S;) {
+                    const u32 wd = o >> 6, b0 = o & 63;
+                    const u32 b1 = (end - S) - (wd << 6) < 64 ? (end - S) - (wd << 6) : 64;
+                    const u64 mk = (b1 == 64 ? ~0ull : ((1ull << b1) - 1)) & ~((1ull << b0) - 1);
+                    atomicOr(&bm[wd], mk);
+                    o = (wd << 6) + b1;
+                }
+            });
+        }
+    }
+    bar();
+    // set bits -> staged edges, in order
+    const u32 wpg = (words + G - 1) / G;
+    const u32 w0 = bits && g * wpg < words ? g * wpg : words, w1 = bits && w0 + wpg < words ? w0 + wpg : words;
+    u32 cnt = 0;
+    if (bits)
+        for (u32 i = w0; i < w1; ++i) cnt += __popcll(bm[i]);
+    u32 tot;
+    const u32 excl = block_excl(sh, bits ? cnt : 0, &tot);
+    if (bits && g == 0) tm[0] = excl;
+    bar();
+    const u32 off = bits ? excl - tm[0] : 0;
+    if (bits && g == G - 1) tm[1] = off + cnt;
+    bar();
+    if (bits && g == 0) {
+        const u32 n = tm[1] ? tm[1] : 1;
+        const u32 slot = x - sh.unit_first;
+        const u32 at = atomicAdd(&sh.stage_top, n);
+        if ((u64)at + n > (u64)c.cap_unit * 8 || slot >= c.cap_unit) {
+            cap_error(sh, IG_CAP_UNIT);
+        } else {
+            c.tab_off[slot] = at;
+            c.tab_cnt[slot] = n;
+            if (tm[1] == 0) {  // no dependency: wait for the synchronisation point
+                c.stage_from[at] = S;
+                c.stage_kind[at] = IG_DEP_SYNC;
+                c.has_succ[S] = 1;
+            }
+        }
+        tm[2] = at;
+    }
+    if (failed(sh)) return;
+    if (bits && cnt) {
+        u32 o = tm[2] + off;
+        for (u32 i = w0; i < w1; ++i) {
+            u64 v = bm[i];
+            while (v) {
+                const u32 bit = __ffsll((long long)v) - 1;
+                v &= v - 1;
+                const u32 from = S + (i << 6) + bit;
+                c.stage_from[o] = from;
+                c.stage_kind[o] = IG_DEP_LIFETIME;
+                c.has_succ[from] = 1;
+                ++o;
+            }
+        }
+    }
+    // the allocation's reader blocks go back to the memory's free list
+    if (act) {
+        AmCell* cl = am_cells(c, a);
+        for (u32 l = l0; l < l1; ++l)
+            if (cl[l].ov) rd_clear(c, m, &cl[l].ov);
+    }
+    bar();
+}
+
 IGN void destroy_buffer(DevCtx& c, Shared& sh, u32 b) {
     unit_begin(c, sh);
     if (tid() == 0) {
-        u32 n = 0;
+        u32 n = 0, most = 0;
         for (u32 m = 2; m < c.n_mem; ++m) {
             const u32 lb = (b * c.n_mem + m) * MAX_LIVE;
             for (u32 i = 0; i < c.live_n[b * c.n_mem + m]; ++i) c.cons_off[n++] = c.live[lb + i];
+            most = c.live_n[b * c.n_mem + m] > most ? c.live_n[b * c.n_mem + m] : most;
         }
+        sh.flag2 = most;
         for (u32 i = 1; i < n; ++i)
             for (u32 j = i; j > 0 && c.cons_off[j] < c.cons_off[j - 1]; --j) {
                 const u32 v = c.cons_off[j];
@@ -2774,19 +3225,23 @@ IGN void destroy_buffer(DevCtx& c, Shared& sh, u32 b) {
         sh.unit_n = n;
     }
     if (failed(sh)) return;
-    const u32 n = sh.unit_n;
-    for (u32 i = 0; i < n; ++i) {
-        DAlloc& a = c.allocs[c.cons_off[i]];
-        if (owner_of(a.mem) != tid()) continue;
-        const u32 x = sh.unit_first + i;
-        put_instr(c, x, IG_FREE, 0, NONE, NONE, b, a.mem, 0xFFFF, c.cons_off[i], 0, a.lo, a.hi);
-        SrcSet s;
-                        ss_init(c, s);
-        free_edges(c, sh, s, a);
-        stage(c, sh, x, s);
-        release_readers(c, a);
-    }
-    bar();
+    const u32 n = sh.unit_n, rounds = sh.flag2;
+    // round r: every memory's r-th FREE (ascending id), by the memory's team
+    const u32 G = team_size(c), TP = nt() / G, ts = tid() / G, g = tid() % G;
+    for (u32 rnd = 0; rnd < rounds; ++rnd)
+        for (u32 base = 0; base < c.n_dev; base += TP) {
+            const u32 m = base + ts + 2;
+            u32 i = 0, seen = 0;
+            bool act = false;
+            if (m < c.n_mem)
+                for (; i < n; ++i)
+                    if (c.allocs[c.cons_off[i]].mem == m && seen++ == rnd) {
+                        act = true;
+                        break;
+                    }
+            team_free(c, sh, act, m, g, G, act ? c.cons_off[i] : 0, sh.unit_first + i);
+            if (failed(sh)) return;
+        }
     unit_end(c, sh);
     if (tid() == 0) {
         DBuf& B = c.bufs[b];

@@ -1,17 +1,22 @@
 """Write the stored expected values of the large parity cases.
 
-Calls only the oracle (oracle/) on the seeded workloads; the GPU tests
-compare the HIP path's counts, per-kind statistics and record digests with
-these files, and its first/last records with the stored ones.
+Calls only the oracle (oracle/) on the seeded workloads; the GPU tests and
+the benchmark compare the HIP path's counts, per-kind statistics and record
+digests with these files, and its first and last records with the stored
+ones.  Each document also keeps the oracle's counts of the algorithmic-bytes
+terms (writer updates, reader insertions, buffer-map updates, mapper boxes),
+which the benchmark's roofline numerator uses.
 
-    python tests/golden/make_golden.py nbody_full growing_q1 ...
-    python tests/golden/make_golden.py batched 4      # the 256 batched streams, 4 processes
+    python tests/golden/make_golden.py nbody_full growing_q8 ...
+    python tests/golden/make_golden.py batched 6      # the 256 batched streams, 6 processes
     python tests/golden/make_golden.py serving 3      # each kind of serving session
 """
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -21,6 +26,7 @@ import oracle  # noqa: E402
 from paper_2503_10516_amd import streams as S  # noqa: E402
 
 CASES = {
+    "stencil1d_full": lambda: S.stencil_1d(),               # 1-D stencil, 4096, 64 tasks, 2 devices
     "nbody_full": lambda: S.nbody(),                       # N-body, 2^20 x 16 B, 500 steps, 16 x 8 devices
     "stencil2d_full": lambda: S.stencil_2d(),               # 2-D stencil, 4096^2, 1000 tasks
     "growing_full": lambda: S.growing(),                    # RSim pattern [84000 x 256], lookahead, unbounded queue
@@ -28,65 +34,57 @@ CASES = {
     "growing_q8": lambda: S.growing(queue_cap=8),           # lookahead window of 8 commands
 }
 
-EDGE_KEEP = 2000  # first and last records stored verbatim
+KEEP = 10000  # first and last records of each list stored verbatim (<case>_records.npz)
 BATCHED_FILE = "batched_digests.json"
+STAT_KEYS = ("n_instructions", "n_bindings", "n_edges", "per_kind", "per_dep", "resizes", "warnings",
+             "digest_instructions", "digest_bindings", "digest_edges", "u_w", "u_r", "u_b", "map_boxes")
 
 
-def rec_list(arr, n):
-    out = []
-    for r in list(arr[:n]) + list(arr[-n:]):
-        out.append([int(x) if not hasattr(x, "__len__") else [int(v) for v in x] for x in r])
-    return out
+def head_tail(arr, n):
+    return np.concatenate([arr[:n], arr[-n:]]) if len(arr) > 2 * n else arr.copy()
 
 
 def main(names):
     for name in names:
         s = CASES[name]()
-        t0 = time.time()
         out = oracle.run_stream(s, fetch=True)
         st = out["stats"]
-        doc = {
-            "case": name,
-            "stream": s.name,
-            "oracle_seconds": round(time.time() - t0, 2),
-            "n_instructions": st["n_instructions"],
-            "n_bindings": st["n_bindings"],
-            "n_edges": st["n_edges"],
-            "per_kind": st["per_kind"],
-            "per_dep": st["per_dep"],
-            "resizes": st["resizes"],
-            "warnings": st["warnings"],
-            "digest_instructions": st["digest_instructions"],
-            "digest_bindings": st["digest_bindings"],
-            "digest_edges": st["digest_edges"],
-            "status": [int(x) for x in out["status"]],
-            "head_tail_instructions": rec_list(out["instructions"], EDGE_KEEP // 4),
-            "head_tail_edges": rec_list(out["edges"], EDGE_KEEP // 2),
-        }
+        doc = {"case": name, "stream": s.name, "oracle_seconds": round(out["seconds"], 2), "keep": KEEP}
+        doc.update({k: st[k] for k in STAT_KEYS})
+        doc["status"] = [int(x) for x in out["status"]]
         with open(os.path.join(HERE, f"{name}.json"), "w") as f:
             json.dump(doc, f)
+        np.savez_compressed(os.path.join(HERE, f"{name}_records.npz"),
+                            instructions=head_tail(out["instructions"], KEEP),
+                            bindings=head_tail(out["bindings"], KEEP),
+                            edges=head_tail(out["edges"], KEEP))
         print(name, st["n_instructions"], st["n_edges"], f"{doc['oracle_seconds']} s", flush=True)
 
 
 def _batched_one(i):
     s = S.batched_stream(S.BATCHED_SEED, i, w_all=S.BATCHED_W_ALL, w_slice=S.BATCHED_W_SLICE)
-    t0 = time.time()
-    st = oracle.run_stream(s, fetch=False)
-    o = st["stats"]
-    return {"index": i, "stream": s.name, "tasks": s.n_tasks, "oracle_seconds": round(time.time() - t0, 2),
-            "n_instructions": o["n_instructions"], "n_bindings": o["n_bindings"], "n_edges": o["n_edges"],
-            "per_kind": o["per_kind"], "per_dep": o["per_dep"], "warnings": o["warnings"],
-            "digest_instructions": o["digest_instructions"], "digest_bindings": o["digest_bindings"],
-            "digest_edges": o["digest_edges"]}
+    r = oracle.run_stream(s, fetch=False)
+    o = r["stats"]
+    row = {"index": i, "stream": s.name, "tasks": s.n_tasks, "oracle_seconds": round(r["seconds"], 2)}
+    row.update({k: o[k] for k in STAT_KEYS})
+    return row
 
 
 def batched(workers):
     """Oracle statistics and digests of every stream of the batched workload
-    (256 streams), computed in parallel worker processes."""
+    (256 streams), computed in parallel worker processes, heaviest first (by
+    the stored timing of a previous run, if any) so the pool stays busy."""
     from multiprocessing import Pool
+    order = list(range(256))
+    try:
+        prev = json.load(open(os.path.join(HERE, BATCHED_FILE)))
+        secs = {r["index"]: r.get("oracle_seconds", 0) for r in prev["streams"]}
+        order.sort(key=lambda i: -secs.get(i, 0))
+    except (OSError, ValueError, KeyError):
+        pass
     with Pool(workers) as pool:
         rows = []
-        for r in pool.imap_unordered(_batched_one, range(256)):
+        for r in pool.imap_unordered(_batched_one, order):
             rows.append(r)
             print(r["index"], r["n_instructions"], r["n_edges"], r["oracle_seconds"], flush=True)
     rows.sort(key=lambda r: r["index"])
@@ -108,9 +106,7 @@ def serving_kinds():
 def _serving_one(i):
     s = serving_kinds()[i]
     st = oracle.run_stream(s, fetch=False)["stats"]
-    keep = ("n_instructions", "n_bindings", "n_edges", "per_kind", "per_dep", "warnings",
-            "digest_instructions", "digest_bindings", "digest_edges")
-    return s.name, {k: st[k] for k in keep}
+    return s.name, {k: st[k] for k in STAT_KEYS}
 
 
 def serving(workers):

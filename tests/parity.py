@@ -66,3 +66,46 @@ def reader_run_stream(variant):
             s.task(1, (0,), (512,), [S.Access(p, S.READ_WRITE, S.ONE_TO_ONE), S.Access(q, S.READ, S.ALL)])
     s.shutdown()
     return s
+
+
+def big_read_stream(variant):
+    """Reads whose regions span hundreds of grid cells on every device (all,
+    slice along dim 0, large fixed boxes), next to neighborhood reads of the
+    same buffer in the same task, before and after them, so that some reads
+    are contained in an earlier large one and some only overlap it; several
+    chunks per device, up to 32 devices.  The large regions are the ones a
+    team of threads scans together."""
+    from paper_2503_10516_amd import streams as S
+    nodes, devices, chunks, dims, ext = [(1, 8, 256, 1, (1 << 13,)), (2, 8, 256, 1, (1 << 12,)),
+                                         (2, 8, 128, 2, (256, 16)), (4, 8, 256, 1, (1 << 12,))][variant]
+    s = S.Stream(nodes, devices, chunks, lookahead=1, queue_cap=8 if variant == 1 else 0,
+                 name=f"big_reads{variant}")
+    bufs = [s.buffer(dims, ext, 4, S.INIT_HOST) for _ in range(3)]
+    lo, hi = (0,) * dims, ext
+    rad = lambda r: tuple(r if d < dims else 0 for d in range(3))
+    half = tuple(e // 2 if d == 0 else e for d, e in enumerate(ext)) + (1,) * (3 - dims)
+    for t in range(18):
+        a, b, c = bufs[t % 3], bufs[(t + 1) % 3], bufs[(t + 2) % 3]
+        acc = [S.Access(a, S.WRITE if t % 2 else S.READ_WRITE, S.ONE_TO_ONE)]
+        k = t % 6
+        if k == 0:
+            acc += [S.Access(b, S.READ, S.NEIGHBORHOOD, rad(1 + t % 3)), S.Access(c, S.READ, S.ALL)]
+        elif k == 1:
+            acc += [S.Access(b, S.READ, S.NEIGHBORHOOD, rad(2)), S.Access(b, S.READ, S.ALL)]
+        elif k == 2:
+            acc += [S.Access(b, S.READ, S.ALL), S.Access(b, S.READ, S.NEIGHBORHOOD, rad(3))]
+        elif k == 3:
+            acc += [S.Access(c, S.READ, S.SLICE, slice_dim=0), S.Access(b, S.READ, S.NEIGHBORHOOD, rad(1))]
+        elif k == 4:
+            acc += [S.Access(b, S.READ, S.FIXED, fixed_lo=(0, 0, 0), fixed_hi=half),
+                    S.Access(b, S.READ, S.NEIGHBORHOOD, rad(4)), S.Access(c, S.READ, S.ONE_TO_ONE)]
+        else:
+            acc += [S.Access(b, S.READ, S.NEIGHBORHOOD, rad(2)), S.Access(c, S.READ, S.FIXED,
+                    fixed_lo=(ext[0] // 4, 0, 0), fixed_hi=tuple(3 * ext[0] // 4 if d == 0 else
+                                                               (ext[d] if d < dims else 1) for d in range(3))),
+                    S.Access(c, S.READ, S.ALL)]
+        s.task(dims, lo, hi, acc)
+        if t == 11:
+            s.epoch()
+    s.shutdown()
+    return s

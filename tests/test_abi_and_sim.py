@@ -14,7 +14,7 @@ import subprocess
 import pytest
 
 import oracle
-from parity import assert_same, reader_run_stream
+from parity import assert_same, big_read_stream, reader_run_stream
 from paper_2503_10516_amd import binding as B
 from paper_2503_10516_amd import streams as S
 
@@ -222,6 +222,15 @@ def test_sim_serving_mix_equals_each_session_alone(sim_lib):
 def test_sim_reader_runs(variant, sim_lib):
     s = reader_run_stream(variant)
     assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), s.name)
+
+
+@pytest.mark.parametrize("variant", range(4))
+@pytest.mark.parametrize("threads", [64, 256])
+def test_sim_big_reads(variant, threads, sim_lib):
+    """Large read regions scanned by thread teams equal the oracle's
+    sequential consumer split."""
+    s = big_read_stream(variant)
+    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=threads), s.name)
 
 
 @pytest.mark.parametrize("index", [0, 3, 7])

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import assert_same, reader_run_stream, record_words
+from parity import assert_same, big_read_stream, reader_run_stream, record_words
 from paper_2503_10516_amd import binding as B
 from paper_2503_10516_amd import streams as S
 
@@ -270,6 +270,17 @@ def test_windowed_batch_matches_oracle():
     bt.close()
 
 
+@pytest.mark.parametrize("variant", range(4))
+@pytest.mark.parametrize("threads", [64, 256, 1024])
+def test_big_reads_team_scans(variant, threads):
+    """Read regions of hundreds of cells scanned by thread teams (coherence),
+    shared source lists of all/slice/fixed reads across the kernels of a
+    device, and buffer destruction by teams: record by record."""
+    s = big_read_stream(variant)
+    want, got = run_both(s, threads=threads)
+    assert_same(want, got, f"{s.name}_t{threads}")
+
+
 @pytest.mark.parametrize("seed", range(40))
 def test_racy_random_streams(seed):
     """Reads of regions that other chunks of the same task write (a user
@@ -282,7 +293,7 @@ def test_racy_random_streams(seed):
 
 # full-size streams of the batched workload with 512-1024 chunks and all or
 # slice reads over up to 128 devices (the workload's heaviest kind of task)
-BATCHED_FULL = [88, 91, 165, 138]
+BATCHED_FULL = [88, 91, 165, 138, 248, 13]
 
 
 def test_batched_full_size_streams_with_all_reads():
