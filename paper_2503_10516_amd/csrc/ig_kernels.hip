@@ -1824,6 +1824,34 @@ IGD u32 team_size(const DevCtx& c) {
 IGN void coherence_count(DevCtx& c, Shared& sh) {
     const u32 A = sh.t_nacc, K = c.per_dev;
     const u32 G = team_size(c);
+    // A read with no cell that is stale on its memory and holds data at the
+    // start of the task needs no copy whatever the consumers before it copy
+    // (copies only add memories to the masks): such reads are found by all
+    // threads at once and skipped by the ordered pass below (cons_x: 0).
+    for (u32 q = tid(); q < c.chunks * A; q += nt()) {
+        const u32 k = q / A, j = q % A, idx = k * IG_MAX_ACCESS + j;
+        const Region& r = c.reg[idx];
+        u32 stale = 0;
+        if (!r.empty && (r.mode & IG_READ)) {
+            const u32 m = mem_of_chunk(c, k);
+            const DBuf& B = c.bufs[r.buffer];
+            const u64* mask = W64(c, B.mask_off);
+            for (u32 i0 = r.clo[0]; i0 < r.chi[0] && !stale; ++i0)
+                for (u32 i1 = r.clo[1]; i1 < r.chi[1] && !stale; ++i1)
+                    for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2) {
+                        const u64* mk = mask + (size_t)cell_of(B, i0, i1, i2) * c.mw;
+                        if ((mk[m >> 6] >> (m & 63)) & 1) continue;
+                        u64 any = 0;
+                        for (u32 w = 0; w < c.mw; ++w) any |= mk[w];
+                        if (any) {
+                            stale = 1;
+                            break;
+                        }
+                    }
+        }
+        c.cons_x[idx] = stale;
+    }
+    bar();
     for (u32 m = tid(); m < c.n_mem; m += nt()) {
         if (m < 2) continue;
         const u32 d = m - 2;
@@ -1851,7 +1879,7 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                 c.cons_cnt[idx] = 0;
                 c.cons_off[idx] = 0;
                 const Region& r = c.reg[idx];
-                if (chunk_empty || r.empty || !(r.mode & IG_READ)) continue;
+                if (chunk_empty || r.empty || !(r.mode & IG_READ) || !c.cons_x[idx]) continue;
                 const u32 b = r.buffer;
                 const u32 key7[7] = {b, r.clo[0], r.clo[1], r.clo[2], r.chi[0], r.chi[1], r.chi[2]};
                 bool again = false;
@@ -2558,12 +2586,18 @@ IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
     }
     bar();
     // reader additions: the threads t with t % n_dev == d share device d's
-    // cells by allocation-local index
+    // cells, member g taking the grid columns i0 = g (mod G) of every
+    // region, each in kernel order
     const u32 nd = c.n_dev, t = tid();
     const u32 d0 = nt() >= nd ? t % nd : t;
     const u32 dstep = nt() >= nd ? nd : nt();
     const u32 g = nt() >= nd ? t / nd : 0;
     const u32 G = nt() >= nd ? (nt() - d0 + nd - 1) / nd : 1;
+    auto own_cells = [&](const Region& rg, const DAlloc& a, auto f) {
+        for (u32 i0 = rg.clo[0] + (g + G - rg.clo[0] % G) % G; i0 < rg.chi[0]; i0 += G)
+            for (u32 i1 = rg.clo[1]; i1 < rg.chi[1]; ++i1)
+                for (u32 i2 = rg.clo[2]; i2 < rg.chi[2]; ++i2) f(alloc_local(a, i0, i1, i2));
+    };
     for (u32 d = d0; d < nd; d += dstep) {
         if (nt() >= nd && d != d0) break;
         const u32 m = d + 2;
@@ -2581,17 +2615,12 @@ IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
                 if (!al) continue;
                 const DAlloc& a = c.allocs[al];
                 AmCell* cl = am_cells(c, a);
-                const u32 n1 = rg.chi[1] - rg.clo[1], n2 = rg.chi[2] - rg.clo[2];
-                const u32 total = (rg.chi[0] - rg.clo[0]) * n1 * n2;
-                for (u32 q = 0; q < total; ++q) {
-                    const u32 i2 = q % n2, i1 = (q / n2) % n1, i0 = q / (n1 * n2);
-                    const u32 l = alloc_local(a, rg.clo[0] + i0, rg.clo[1] + i1, rg.clo[2] + i2);
-                    if (l % G != g) continue;
+                own_cells(rg, a, [&](u32 l) {
                     if (nk == 1)
                         cell_add_reader_at(c, sh, m, cl + l, am_load(cl + l), first);
                     else
                         rd_append_range(c, sh, m, &cl[l].ov, first, nk);
-                }
+                });
             }
         }
         for (u32 k = d * K; k < (d + 1) * K; ++k) {
@@ -2605,16 +2634,11 @@ IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
                 if (!al) continue;
                 const DAlloc& a = c.allocs[al];
                 AmCell* cl = am_cells(c, a);
-                const u32 n1 = rg.chi[1] - rg.clo[1], n2 = rg.chi[2] - rg.clo[2];
-                const u32 total = (rg.chi[0] - rg.clo[0]) * n1 * n2;
-                for (u32 q = 0; q < total; ++q) {
-                    const u32 i2 = q % n2, i1 = (q / n2) % n1, i0 = q / (n1 * n2);
-                    const u32 l = alloc_local(a, rg.clo[0] + i0, rg.clo[1] + i1, rg.clo[2] + i2);
-                    if (l % G != g) continue;
+                own_cells(rg, a, [&](u32 l) {
                     const AmCell e = am_load(cl + l);
-                    if ((e.w & ~W_ALLOC) == x) continue;  // written by this kernel: no reader remains
+                    if ((e.w & ~W_ALLOC) == x) return;  // written by this kernel: no reader remains
                     cell_add_reader_at(c, sh, m, cl + l, e, x);
-                }
+                });
             }
         }
     }
