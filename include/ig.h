@@ -347,8 +347,14 @@ ig_status ig_fetch_edges(ig_context* ctx, ig_edge* dst, size_t cap, size_t* n_ou
 ig_status ig_fetch_task_status(ig_context* ctx, int32_t* dst, size_t cap, size_t* n_out);
 
 /* Per-task timing from the device clock, in nanoseconds relative to the
- * first task's intake: dst[2*i] = intake of task i began, dst[2*i+1] = its
- * records were complete (after any lookahead holding).  cap = tasks. */
+ * first task's intake, four values per task i:
+ *   dst[4*i+0]  intake began (structural checks, Sec. 4.4 checks)
+ *   dst[4*i+1]  intake ended: the task was compiled at once or entered the
+ *               lookahead queue (Sec. 4.3)
+ *   dst[4*i+2]  its compilation began (after any lookahead holding)
+ *   dst[4*i+3]  its records were complete
+ * so dst[4*i+2] - dst[4*i+1] is the time the lookahead held the task.  A
+ * rejected task has all of the last three equal.  cap = tasks. */
 ig_status ig_fetch_task_times(ig_context* ctx, double* dst, size_t cap, size_t* n_out);
 
 /* Per-kind counts, resizes, warnings and the three record digests, all

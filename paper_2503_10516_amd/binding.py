@@ -379,9 +379,10 @@ class Context:
         )
 
     def task_times_ns(self) -> np.ndarray:
-        """(n_tasks, 2): intake start and completion of each task, ns."""
+        """(n_tasks, 4) ns per task: intake start, intake end (compiled at
+        once or queued), compilation start, records complete."""
         nt = self.counts()[3]
-        arr = np.zeros((nt, 2), dtype=np.float64)
+        arr = np.zeros((nt, 4), dtype=np.float64)
         got = ctypes.c_size_t()
         st = self.L.ig_fetch_task_times(self.h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nt,
                                         ctypes.byref(got))

@@ -123,6 +123,8 @@ static u64 carve(const Caps& k, char* base, DevCtx* h, Tail* tail = nullptr) {
     TAKE(has_succ, u8, k.cap_instr);
     TAKE(task_status, i32, k.cap_cmds);
     TAKE(task_t0, u64, k.cap_cmds);
+    TAKE(task_tq, u64, k.cap_cmds);
+    TAKE(task_tc, u64, k.cap_cmds);
     TAKE(task_t1, u64, k.cap_cmds);
     TAKE(phase, u64, 32);
     TAKE(bufs, DBuf, MAX_BUF);
@@ -714,19 +716,17 @@ ig_status ig_fetch_task_times(ig_context* c, double* dst, size_t cap, size_t* n_
     const ig_status st = refresh(c);
     if (st != IG_OK) return st;
     const u64 n = std::min<u64>(cap, c->s.n_tasks);
-    std::vector<u64> t0(n), t1(n);
-    if (n) {
-        if (igrt::copy_d2h(t0.data(), c->h.task_t0, n * sizeof(u64), c->stream) != 0 ||
-            igrt::copy_d2h(t1.data(), c->h.task_t1, n * sizeof(u64), c->stream) != 0 ||
-            igrt::stream_sync(c->stream) != 0)
-            return IG_E_DEVICE;
+    std::vector<u64> t[4];
+    u64* src[4] = {c->h.task_t0, c->h.task_tq, c->h.task_tc, c->h.task_t1};
+    for (int q = 0; q < 4; ++q) {
+        t[q].resize(n);
+        if (n && igrt::copy_d2h(t[q].data(), src[q], n * sizeof(u64), c->stream) != 0) return IG_E_DEVICE;
     }
+    if (n && igrt::stream_sync(c->stream) != 0) return IG_E_DEVICE;
     const double khz = igrt::clock_khz();
     if (khz <= 0) return IG_E_DEVICE;
-    for (u64 i = 0; i < n; ++i) {
-        dst[2 * i] = (double)(t0[i] - t0[0]) / khz * 1e6;
-        dst[2 * i + 1] = (double)(t1[i] - t0[0]) / khz * 1e6;
-    }
+    for (u64 i = 0; i < n; ++i)
+        for (int q = 0; q < 4; ++q) dst[4 * i + q] = (double)(t[q][i] - t[0][0]) / khz * 1e6;
     if (n_out) *n_out = (size_t)n;
     return IG_OK;
 }

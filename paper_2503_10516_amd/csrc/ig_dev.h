@@ -263,6 +263,8 @@ struct DevCtx {
     u8* has_succ;
     i32* task_status;
     u64* task_t0;   // [cap_cmds] device clock when the task's intake began
+    u64* task_tq;   // [cap_cmds] device clock when its intake ended (compiled at once or queued)
+    u64* task_tc;   // [cap_cmds] device clock when its compilation began
     u64* task_t1;   // [cap_cmds] device clock when its records were complete
     u64* phase;     // [32] device-clock ticks per analysis phase (profiling builds only)
     // --- state ---

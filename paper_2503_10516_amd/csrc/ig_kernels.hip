@@ -2732,6 +2732,7 @@ IGN void compile_task(DevCtx& c, Shared& sh, u32 ci, bool fresh) {
         compute_regions(c, sh);
         covered = regions_covered(c, sh);
     }
+    if (tid() == 0) c.task_tc[sh.t_id] = ig_clock();
     unit_begin(c, sh);
     tick(c, sh, PH_COMPILE_REGIONS);
     if (!covered) {
@@ -2992,7 +2993,10 @@ IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
         sh.s.n_tasks += 1;
         if (overlap) {
             sh.s.rejected += 1;
-            c.task_t1[sh.t_id] = ig_clock();
+            const u64 now = ig_clock();
+            c.task_tq[sh.t_id] = now;
+            c.task_tc[sh.t_id] = now;
+            c.task_t1[sh.t_id] = now;
         }
         if (st == IG_W_UNINIT_READ) sh.s.warnings += 1;
     }
@@ -3016,6 +3020,7 @@ IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
     if (tid() == 0) sh.t_covered = (sh.s.qlen == 0 && !allocating) ? 1u : 0u;
     bar();
     tick(c, sh, PH_LOOKAHEAD);
+    if (tid() == 0) c.task_tq[sh.t_id] = ig_clock();
     push_command(c, sh, ci, allocating);
     if (failed(sh)) return;
     if (tid() == 0) {
