@@ -53,7 +53,8 @@ typedef int32_t ig_status;
 #define IG_E_OVERLAPPING_WRITE (-2)  /* Sec. 4.4: chunks of one task write overlapping regions */
 #define IG_E_CAPACITY (-3)           /* a device-side table or the arena is too small */
 #define IG_E_DEVICE (-4)             /* a HIP runtime error */
-#define IG_E_BUSY (-5)               /* serving admission: no free slot */
+#define IG_E_BUSY (-5)               /* serving admission: no free slot or arena memory */
+#define IG_E_INTERNAL (-6)           /* an invariant of the analysis state failed (a library bug) */
 
 /* Which capacity an IG_E_CAPACITY raised during analysis ran out of
  * (ig_stats.capacity_exceeded, ig_progress.capacity_exceeded). */
@@ -328,6 +329,79 @@ typedef struct ig_graph ig_graph;
 ig_status ig_batch_graph_create(ig_context* const* ctxs, size_t n, void* stream, ig_graph** out);
 ig_status ig_graph_launch(ig_graph* graph, void* stream);
 ig_status ig_graph_destroy(ig_graph* graph);
+
+/* ---------------------------------------------------------------------------
+ * Serving (continuous batching).  Sessions are independent streams, each in
+ * its own context, so a session's records are the same alone and in the mix
+ * (ids are per context).  A server holds up to `slots` sessions and a budget
+ * of arena bytes; a session is admitted when a slot and its arena bytes are
+ * free, recorded into while earlier launches run, and analysed in batched
+ * launches over every session with new commands (one workgroup each),
+ * queued asynchronously on the server's stream: commands travel through
+ * pinned staging, progress comes back through pinned memory and an event,
+ * and admission prepares the new context on a side stream, so no call but
+ * a waiting poll blocks on the device.
+ * --------------------------------------------------------------------------- */
+typedef struct ig_server ig_server;
+
+typedef struct ig_server_desc {
+    uint32_t slots;         /* sessions held at once, 1..4096 */
+    uint32_t threads;       /* workgroup size of every session (0: 256) */
+    uint32_t window;        /* commands per session per launch (0: all recorded) */
+    uint32_t max_inflight;  /* launches queued on the stream at once, 1..8 (0: 2) */
+    uint64_t arena_budget;  /* arena bytes (ig_arena_bytes) all sessions may take together, whoever
+                               provides the memory (0: unbounded) */
+    uint64_t stage_bytes;   /* pinned staging of commands per launch (0: 8 MiB; at least one command) */
+    void* stream;           /* hipStream_t of the launches (NULL: the default stream) */
+} ig_server_desc;
+
+/* What a poll reports for one occupied slot (from the latest collected
+ * launch that included it). */
+typedef struct ig_session_progress {
+    uint32_t slot;
+    uint32_t in_flight;          /* part of a launch not collected yet */
+    uint64_t tasks_done;         /* leading tasks whose records are complete (fetchable) */
+    uint64_t tasks_seen;         /* tasks analysed (queued or compiled) */
+    int32_t error;               /* a negative status raised during analysis, else 0 */
+    uint32_t finished;           /* shutdown analysed */
+    uint32_t commands_done;      /* recorded commands analysed */
+    uint32_t commands_recorded;  /* recorded commands */
+} ig_session_progress; /* 40 bytes */
+
+/* Create / destroy a server.  Destroy waits for the queued launches and
+ * destroys the contexts still held.  Errors: IG_E_INVALID, IG_E_DEVICE. */
+ig_status ig_server_create(const ig_server_desc* desc, ig_server** out);
+ig_status ig_server_destroy(ig_server* srv);
+
+/* Admission: a context for `desc` (its stream is replaced by the server's;
+ * desc->threads must equal the server's or be 0) in a free slot.  IG_E_BUSY
+ * when every slot is taken or its arena would exceed the budget; the caller
+ * polls and tries again.  Errors: IG_E_INVALID, IG_E_DEVICE, IG_E_CAPACITY. */
+ig_status ig_server_admit(ig_server* srv, const ig_context_desc* desc, uint32_t* out_slot);
+
+/* The session's context, for the recording calls (ig_buffer_create,
+ * ig_buffer_destroy, ig_epoch, ig_shutdown, fetch and stats after it is
+ * detached).  Do not call ig_flush_window, ig_sync or ig_rewind on it while
+ * it is held by the server.  Errors: IG_E_INVALID (free slot). */
+ig_status ig_server_session(ig_server* srv, uint32_t slot, ig_context** out);
+
+/* Record a task into a session (= ig_submit_task on its context). */
+ig_status ig_server_submit(ig_server* srv, uint32_t slot, const ig_task_desc* task, uint64_t* out_task);
+
+/* Collect finished launches and queue new ones: every launch whose event
+ * has completed is collected (wait != 0: the oldest queued launch is waited
+ * for first); then, while fewer than max_inflight launches are queued, one
+ * launch covers every session with commands that no queued launch covers
+ * (uploading what fits in the staging).  out receives one entry per
+ * occupied slot (at most cap); *n_out the number written.  Errors:
+ * IG_E_INVALID, IG_E_DEVICE. */
+ig_status ig_server_poll(ig_server* srv, uint32_t wait, ig_session_progress* out, size_t cap, size_t* n_out);
+
+/* Detach a session whose launches have been collected: its slot and arena
+ * budget are freed, and the context (with its records) passes to the
+ * caller, who destroys it with ig_context_destroy.  IG_E_BUSY while a
+ * queued launch covers it.  Errors: IG_E_INVALID. */
+ig_status ig_server_detach(ig_server* srv, uint32_t slot, ig_context** out);
 
 /* Wait for the context's outstanding work; reports IG_E_CAPACITY or
  * IG_E_DEVICE raised during analysis. */

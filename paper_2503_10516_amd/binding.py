@@ -27,6 +27,7 @@ EDGE_DTYPE = np.dtype([("from", "<u8"), ("to", "<u8"), ("kinds", "<u4"), ("pad",
 
 IG_OK, IG_W_UNINIT_READ, IG_E_INVALID, IG_E_OVERLAPPING_WRITE, IG_E_CAPACITY, IG_E_DEVICE, IG_E_BUSY = \
     0, 1, -1, -2, -3, -4, -5
+IG_E_INTERNAL = -6
 
 
 class IgError(RuntimeError):
@@ -82,7 +83,8 @@ EXPORTS = [
     "ig_fetch_instructions", "ig_fetch_bindings", "ig_fetch_edges", "ig_fetch_task_status",
     "ig_fetch_task_times", "ig_stats_get", "ig_status_str", "ig_batch_rewind", "ig_batch_progress",
     "ig_batch_graph_create", "ig_graph_launch", "ig_graph_destroy", "ig_batch_flush_window",
-    "ig_batch_progress_noalloc",
+    "ig_batch_progress_noalloc", "ig_server_create", "ig_server_destroy", "ig_server_admit", "ig_server_session",
+    "ig_server_submit", "ig_server_poll", "ig_server_detach",
 ]
 
 _libs: Dict[str, ctypes.CDLL] = {}
@@ -114,6 +116,13 @@ def lib(path: Optional[str] = None) -> ctypes.CDLL:
     L.ig_batch_rewind.argtypes = [P(vp), ctypes.c_size_t, vp]
     L.ig_batch_progress.argtypes = [P(vp), ctypes.c_size_t, vp, vp]
     L.ig_batch_progress_noalloc.argtypes = [P(vp), ctypes.c_size_t, vp, vp]
+    L.ig_server_create.argtypes = [vp, P(vp)]
+    L.ig_server_destroy.argtypes = [vp]
+    L.ig_server_admit.argtypes = [vp, P(ContextDesc), P(ctypes.c_uint32)]
+    L.ig_server_session.argtypes = [vp, ctypes.c_uint32, P(vp)]
+    L.ig_server_submit.argtypes = [vp, ctypes.c_uint32, P(TaskDesc), P(ctypes.c_uint64)]
+    L.ig_server_poll.argtypes = [vp, ctypes.c_uint32, vp, ctypes.c_size_t, P(ctypes.c_size_t)]
+    L.ig_server_detach.argtypes = [vp, ctypes.c_uint32, P(vp)]
     L.ig_batch_graph_create.argtypes = [P(vp), ctypes.c_size_t, vp, P(vp)]
     L.ig_graph_launch.argtypes = [vp, vp]
     L.ig_graph_destroy.argtypes = [vp]
@@ -230,6 +239,32 @@ def estimate_caps(stream, margin: float = 2.0, floor: int = 4096) -> Dict[str, i
                 cap_edges=int(margin * e) + 4 * floor)
 
 
+def context_desc(L, device, stream=None, **kw):
+    """A context descriptor; on "cuda" with its arena as a torch tensor and
+    torch's (or the given) stream.  Returns (desc, arena, stream)."""
+    d = ContextDesc()
+    d.nodes, d.devices_per_node, d.chunks = kw["nodes"], kw["devices"], kw.get("chunks", 0)
+    d.horizon_step, d.lookahead = kw.get("horizon_step", 0), kw.get("lookahead", 1)
+    d.flush_horizons, d.queue_cap = kw.get("flush_horizons", 0), kw.get("queue_cap", 0)
+    d.threads = kw.get("threads", 0)
+    d.cap_commands, d.cap_instructions = kw.get("cap_commands", 0), kw.get("cap_instructions", 0)
+    d.cap_edges, d.cap_state_words = kw.get("cap_edges", 0), kw.get("cap_state_words", 0)
+    d.cap_unit, d.cap_scratch = kw.get("cap_unit", 0), kw.get("cap_scratch", 0)
+    arena, s = None, None
+    if device == "cuda":
+        import torch
+        nbytes = ctypes.c_uint64()
+        st = L.ig_arena_bytes(ctypes.byref(d), ctypes.byref(nbytes))
+        if st != 0:
+            raise IgError("ig_arena_bytes", st)
+        arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+        d.arena = arena.data_ptr()
+        d.arena_bytes = nbytes.value
+        s = stream if stream is not None else torch.cuda.current_stream()
+        d.stream = s.cuda_stream
+    return d, arena, s
+
+
 class Context:
     """One stream analysed by libig.
 
@@ -241,33 +276,27 @@ class Context:
                  queue_cap=0, threads=0, lib_path=None, device=None, cap_commands=0,
                  cap_instructions=0, cap_edges=0, cap_state_words=0, cap_unit=0, cap_scratch=0, stream=None):
         self.L = lib(lib_path)
-        d = ContextDesc()
-        d.nodes, d.devices_per_node, d.chunks = nodes, devices, chunks
-        d.horizon_step, d.lookahead, d.flush_horizons, d.queue_cap = horizon_step, lookahead, flush_horizons, queue_cap
-        d.threads = threads
-        d.cap_commands, d.cap_instructions, d.cap_edges = cap_commands, cap_instructions, cap_edges
-        d.cap_state_words, d.cap_unit, d.cap_scratch = cap_state_words, cap_unit, cap_scratch
-        self.arena = None
         if device is None:
             device = "cuda" if lib_path is None else "host"
         self.device = device
-        if device == "cuda":
-            import torch
-            nbytes = ctypes.c_uint64()
-            st = self.L.ig_arena_bytes(ctypes.byref(d), ctypes.byref(nbytes))
-            if st != 0:
-                raise IgError("ig_arena_bytes", st)
-            self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
-            d.arena = self.arena.data_ptr()
-            d.arena_bytes = nbytes.value
-            s = stream if stream is not None else torch.cuda.current_stream()
-            d.stream = s.cuda_stream
-            self.torch_stream = s
+        d, self.arena, self.torch_stream = context_desc(
+            self.L, device, stream, nodes=nodes, devices=devices, chunks=chunks, horizon_step=horizon_step,
+            lookahead=lookahead, flush_horizons=flush_horizons, queue_cap=queue_cap, threads=threads,
+            cap_commands=cap_commands, cap_instructions=cap_instructions, cap_edges=cap_edges,
+            cap_state_words=cap_state_words, cap_unit=cap_unit, cap_scratch=cap_scratch)
         self.desc = d
         self.h = ctypes.c_void_p()
         st = self.L.ig_context_create(ctypes.byref(d), ctypes.byref(self.h))
         if st != 0:
             raise IgError("ig_context_create", st)
+
+    @classmethod
+    def wrap(cls, L, handle, desc, arena, device) -> "Context":
+        """A Context object owning an existing context handle (a session
+        detached from a server)."""
+        c = cls.__new__(cls)
+        c.L, c.h, c.desc, c.arena, c.device, c.torch_stream = L, handle, desc, arena, device, None
+        return c
 
     # --- recording ---------------------------------------------------------
     def buffer_create(self, dims, extent, elem_size, init) -> int:
@@ -520,3 +549,105 @@ def batch_flush(contexts: Sequence[Context], stream=None, window: int = 0) -> No
     st = contexts[0].L.ig_batch_flush_window(_ctx_array(contexts), len(contexts), _stream_ptr(stream), window)
     if st != 0:
         raise IgError("ig_batch_flush_window", st)
+
+
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_uint32), ("threads", ctypes.c_uint32), ("window", ctypes.c_uint32),
+                ("max_inflight", ctypes.c_uint32), ("arena_budget", ctypes.c_uint64),
+                ("stage_bytes", ctypes.c_uint64), ("stream", ctypes.c_void_p)]
+
+
+class SessionProgress(ctypes.Structure):
+    _fields_ = [("slot", ctypes.c_uint32), ("in_flight", ctypes.c_uint32), ("tasks_done", ctypes.c_uint64),
+                ("tasks_seen", ctypes.c_uint64), ("error", ctypes.c_int32), ("finished", ctypes.c_uint32),
+                ("commands_done", ctypes.c_uint32), ("commands_recorded", ctypes.c_uint32)]
+
+
+assert ctypes.sizeof(SessionProgress) == 40
+
+
+class Server:
+    """ig_server_*: sessions admitted into slots, analysed in batched
+    launches queued asynchronously (continuous batching)."""
+
+    def __init__(self, slots: int, threads: int = 256, window: int = 0, max_inflight: int = 2,
+                 arena_budget: int = 0, stage_bytes: int = 0, lib_path: Optional[str] = None, stream=None):
+        self.L = lib(lib_path)
+        self.device = "cuda" if lib_path is None else "host"
+        d = ServerDesc(slots, threads, window, max_inflight, arena_budget, stage_bytes, None)
+        self.stream = None
+        if self.device == "cuda":
+            import torch
+            self.stream = stream if stream is not None else torch.cuda.current_stream()
+            d.stream = self.stream.cuda_stream
+        self.slots = slots
+        self.h = ctypes.c_void_p()
+        st = self.L.ig_server_create(ctypes.byref(d), ctypes.byref(self.h))
+        if st != 0:
+            raise IgError("ig_server_create", st)
+        self.sessions: Dict[int, tuple] = {}  # slot -> (desc, arena)
+        self._out = (SessionProgress * slots)()
+
+    def admit(self, stream_obj, threads: int = 0, **caps) -> Optional[int]:
+        """Admit a session for a Stream (its cluster shape and lookahead
+        settings; no command is recorded).  None when the server is busy."""
+        kw = stream_obj.desc()
+        kw.update(caps)
+        kw["threads"] = threads
+        d, arena, _ = context_desc(self.L, self.device, self.stream, **kw)
+        slot = ctypes.c_uint32()
+        st = self.L.ig_server_admit(self.h, ctypes.byref(d), ctypes.byref(slot))
+        if st == IG_E_BUSY:
+            return None
+        if st != 0:
+            raise IgError("ig_server_admit", st)
+        self.sessions[slot.value] = (d, arena)
+        return slot.value
+
+    def context(self, slot: int) -> "Context":
+        """A non-owning view of the session's context, for recording."""
+        h = ctypes.c_void_p()
+        st = self.L.ig_server_session(self.h, slot, ctypes.byref(h))
+        if st != 0:
+            raise IgError("ig_server_session", st)
+        d, arena = self.sessions[slot]
+        c = Context.wrap(self.L, h, d, arena, self.device)
+        c.close = lambda: None  # the server owns it
+        return c
+
+    def submit(self, slot: int, td: "TaskDesc") -> None:
+        st = self.L.ig_server_submit(self.h, slot, ctypes.byref(td), None)
+        if st != 0:
+            raise IgError("ig_server_submit", st)
+
+    def poll(self, wait: bool = False) -> List[SessionProgress]:
+        n = ctypes.c_size_t()
+        st = self.L.ig_server_poll(self.h, 1 if wait else 0, ctypes.cast(self._out, ctypes.c_void_p), self.slots,
+                                   ctypes.byref(n))
+        if st != 0:
+            raise IgError("ig_server_poll", st)
+        return [self._out[i] for i in range(n.value)]
+
+    def detach(self, slot: int) -> Optional["Context"]:
+        """The session's context, owned by the caller from now on (None
+        while a queued launch covers it)."""
+        h = ctypes.c_void_p()
+        st = self.L.ig_server_detach(self.h, slot, ctypes.byref(h))
+        if st == IG_E_BUSY:
+            return None
+        if st != 0:
+            raise IgError("ig_server_detach", st)
+        d, arena = self.sessions.pop(slot)
+        return Context.wrap(self.L, h, d, arena, self.device)
+
+    def close(self) -> None:
+        if self.h:
+            self.L.ig_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+        self.sessions = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

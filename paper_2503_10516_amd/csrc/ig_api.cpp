@@ -245,6 +245,7 @@ const char* ig_status_str(ig_status st) {
         case IG_E_CAPACITY: return "capacity exceeded";
         case IG_E_DEVICE: return "device error";
         case IG_E_BUSY: return "busy";
+        case IG_E_INTERNAL: return "internal invariant failed";
         default: return "unknown status";
     }
 }
@@ -631,6 +632,256 @@ ig_status ig_graph_destroy(ig_graph* g) {
     igrt::dev_free(g->table);
     delete g;
     return rc ? IG_E_DEVICE : IG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Serving
+// ---------------------------------------------------------------------------
+struct ig_server {
+    ig_server_desc d;
+    void* side = nullptr;                  // stream for preparing admitted contexts
+    std::vector<ig_context*> slot;         // nullptr: free
+    std::vector<u64> bytes;                // arena bytes per slot
+    std::vector<ig_session_progress> last; // latest collected progress per slot
+    std::vector<int> inflight_n;           // queued launches covering the slot
+    u64 used = 0;
+    struct Launch {
+        void* ev = nullptr;
+        char* host = nullptr;              // pinned: table | progress words | cmd_end words | commands
+        char* dev = nullptr;               // device: table | progress words
+        std::vector<u32> slots;
+        bool busy = false;
+    };
+    std::vector<Launch> ring;
+    size_t next = 0;                       // ring entry of the next launch
+    size_t oldest = 0;                     // ring entry of the oldest queued launch
+    size_t queued = 0;
+    u64 host_bytes = 0, dev_bytes = 0;
+};
+
+static size_t srv_table_bytes(const ig_server* s) { return ((size_t)s->d.slots * sizeof(DevCtx*) + 255) & ~(size_t)255; }
+static size_t srv_prog_bytes(const ig_server* s) { return ((size_t)s->d.slots * 32 + 255) & ~(size_t)255; }
+static size_t srv_end_bytes(const ig_server* s) { return ((size_t)s->d.slots * 4 + 255) & ~(size_t)255; }
+
+static void srv_free(ig_server* s) {
+    for (auto& L : s->ring) {
+        if (L.ev) igrt::event_destroy(L.ev);
+        if (L.host) igrt::host_free_pinned(L.host);
+        if (L.dev) igrt::dev_free(L.dev);
+    }
+    if (s->side) igrt::stream_destroy(s->side);
+    delete s;
+}
+
+ig_status ig_server_create(const ig_server_desc* desc, ig_server** out) {
+    if (!desc || !out || desc->slots == 0 || desc->slots > 4096 || desc->max_inflight > 8) return IG_E_INVALID;
+    const u32 threads = desc->threads ? desc->threads : 256;
+    if (threads < 64 || threads > MAX_THREADS || (threads & 63)) return IG_E_INVALID;
+    ig_server* s = new (std::nothrow) ig_server();
+    if (!s) return IG_E_CAPACITY;
+    s->d = *desc;
+    s->d.threads = threads;
+    s->d.max_inflight = desc->max_inflight ? desc->max_inflight : 2;
+    s->d.stage_bytes = std::max<u64>(desc->stage_bytes ? desc->stage_bytes : (8ull << 20), sizeof(DevCmd));
+    s->slot.assign(s->d.slots, nullptr);
+    s->bytes.assign(s->d.slots, 0);
+    s->last.assign(s->d.slots, ig_session_progress{});
+    s->inflight_n.assign(s->d.slots, 0);
+    s->host_bytes = srv_table_bytes(s) + srv_prog_bytes(s) + srv_end_bytes(s) + s->d.stage_bytes;
+    s->dev_bytes = srv_table_bytes(s) + srv_prog_bytes(s);
+    s->ring.resize(s->d.max_inflight);
+    if (igrt::stream_create(&s->side) != 0) {
+        s->side = nullptr;
+        srv_free(s);
+        return IG_E_DEVICE;
+    }
+    for (auto& L : s->ring) {
+        void* h = nullptr;
+        void* dv = nullptr;
+        if (igrt::event_create(&L.ev) != 0) L.ev = nullptr;
+        if (igrt::host_malloc_pinned(&h, s->host_bytes) == 0) L.host = (char*)h;
+        if (igrt::dev_malloc(&dv, s->dev_bytes) == 0) L.dev = (char*)dv;
+        if (!L.ev || !L.host || !L.dev) {
+            srv_free(s);
+            return IG_E_DEVICE;
+        }
+    }
+    *out = s;
+    return IG_OK;
+}
+
+ig_status ig_server_destroy(ig_server* s) {
+    if (!s) return IG_E_INVALID;
+    for (auto& L : s->ring)
+        if (L.busy) igrt::event_sync(L.ev);
+    igrt::stream_sync(s->d.stream);
+    for (ig_context* c : s->slot)
+        if (c) ig_context_destroy(c);
+    srv_free(s);
+    return IG_OK;
+}
+
+ig_status ig_server_admit(ig_server* s, const ig_context_desc* desc, uint32_t* out_slot) {
+    if (!s || !desc || !out_slot) return IG_E_INVALID;
+    if (desc->threads && desc->threads != s->d.threads) return IG_E_INVALID;
+    ig_context_desc d = *desc;
+    d.threads = s->d.threads;
+    d.stream = s->side;
+    uint64_t need = 0;
+    const ig_status st = ig_arena_bytes(&d, &need);
+    if (st != IG_OK) return st;
+    u32 free_slot = NONE;
+    for (u32 i = 0; i < s->d.slots && free_slot == NONE; ++i)
+        if (!s->slot[i]) free_slot = i;
+    if (free_slot == NONE) return IG_E_BUSY;
+    if (s->d.arena_budget && s->used + need > s->d.arena_budget) return IG_E_BUSY;
+    ig_context* c = nullptr;
+    const ig_status cs = ig_context_create(&d, &c);  // prepared (and synchronised) on the side stream
+    if (cs != IG_OK) return cs;
+    c->stream = s->d.stream;
+    s->slot[free_slot] = c;
+    s->bytes[free_slot] = need;
+    s->used += need;
+    s->inflight_n[free_slot] = 0;
+    ig_session_progress& p = s->last[free_slot];
+    std::memset(&p, 0, sizeof p);
+    p.slot = free_slot;
+    *out_slot = free_slot;
+    return IG_OK;
+}
+
+ig_status ig_server_session(ig_server* s, uint32_t slot, ig_context** out) {
+    if (!s || !out || slot >= s->d.slots || !s->slot[slot]) return IG_E_INVALID;
+    *out = s->slot[slot];
+    return IG_OK;
+}
+
+ig_status ig_server_submit(ig_server* s, uint32_t slot, const ig_task_desc* task, uint64_t* out_task) {
+    if (!s || slot >= s->d.slots || !s->slot[slot]) return IG_E_INVALID;
+    return ig_submit_task(s->slot[slot], task, out_task);
+}
+
+ig_status ig_server_detach(ig_server* s, uint32_t slot, ig_context** out) {
+    if (!s || !out || slot >= s->d.slots || !s->slot[slot]) return IG_E_INVALID;
+    if (s->inflight_n[slot]) return IG_E_BUSY;
+    ig_context* c = s->slot[slot];
+    // a detached context is used on its own from now on: progress known,
+    // scalars read afresh
+    c->s_valid = false;
+    s->slot[slot] = nullptr;
+    s->used -= s->bytes[slot];
+    s->bytes[slot] = 0;
+    *out = c;
+    return IG_OK;
+}
+
+// Collect the oldest queued launch (its event has completed).
+static void srv_collect(ig_server* s) {
+    ig_server::Launch& L = s->ring[s->oldest];
+    const u64* w = (const u64*)(L.host + srv_table_bytes(s));
+    for (size_t i = 0; i < L.slots.size(); ++i) {
+        const u32 q = L.slots[i];
+        s->inflight_n[q] -= 1;
+        if (!s->slot[q]) continue;
+        ig_session_progress& p = s->last[q];
+        p.tasks_done = w[4 * i] & 0xFFFFFFFFu;
+        p.tasks_seen = w[4 * i] >> 32;
+        p.error = (int32_t)(uint32_t)(w[4 * i + 1] & 0xFFFFFFFFu);
+        p.finished = (uint32_t)w[4 * i + 2];
+        p.commands_done = (uint32_t)w[4 * i + 3];
+    }
+    L.busy = false;
+    L.slots.clear();
+    s->oldest = (s->oldest + 1) % s->ring.size();
+    s->queued -= 1;
+}
+
+// Queue one launch over the sessions with commands no queued launch covers.
+static ig_status srv_launch(ig_server* s, bool* launched) {
+    *launched = false;
+    ig_server::Launch& L = s->ring[s->next];
+    char* table_h = L.host;
+    char* end_h = L.host + srv_table_bytes(s) + srv_prog_bytes(s);
+    char* stage = end_h + srv_end_bytes(s);
+    u64 stage_used = 0;
+    std::vector<DevCtx*> ptrs;
+    L.slots.clear();
+    for (u32 q = 0; q < s->d.slots; ++q) {
+        ig_context* c = s->slot[q];
+        if (!c) continue;
+        // new commands go into this launch (launches of one stream run in
+        // order); commands a collected launch left unanalysed (the window)
+        // go in only while no queued launch covers the session
+        const size_t rec = c->cmds.size();
+        const bool unanalysed = !s->inflight_n[q] && s->last[q].commands_done < c->uploaded;
+        size_t n = rec - c->uploaded;
+        if (n == 0 && !unanalysed) continue;
+        const u64 room = (s->d.stage_bytes - stage_used) / sizeof(DevCmd);
+        if (n > room) n = (size_t)room;
+        if (n == 0 && !unanalysed) continue;
+        if (n) {
+            std::memcpy(stage + stage_used, c->cmds.data() + c->uploaded, n * sizeof(DevCmd));
+            if (igrt::copy_h2d(c->h.cmds + c->uploaded, stage + stage_used, n * sizeof(DevCmd), s->d.stream) != 0)
+                return IG_E_DEVICE;
+            stage_used += n * sizeof(DevCmd);
+            c->uploaded += n;
+            u32* endw = (u32*)end_h + L.slots.size();
+            *endw = (u32)c->uploaded;
+            if (igrt::copy_h2d(&c->dctx->cmd_end, endw, sizeof(u32), s->d.stream) != 0) return IG_E_DEVICE;
+            c->h.cmd_end = (u32)c->uploaded;
+        }
+        ptrs.push_back(c->dctx);
+        L.slots.push_back(q);
+    }
+    if (L.slots.empty()) return IG_OK;
+    std::memcpy(table_h, ptrs.data(), ptrs.size() * sizeof(DevCtx*));
+    DevCtx** table_d = (DevCtx**)L.dev;
+    uint64_t* prog_d = (uint64_t*)(L.dev + srv_table_bytes(s));
+    char* prog_h = L.host + srv_table_bytes(s);
+    const unsigned n = (unsigned)L.slots.size();
+    if (igrt::copy_h2d(table_d, table_h, n * sizeof(DevCtx*), s->d.stream) != 0 ||
+        igrt::launch_analyse(table_d, n, s->d.threads, s->d.window, s->d.stream) != 0 ||
+        igrt::launch_gather(table_d, n, prog_d, s->d.stream) != 0 ||
+        igrt::copy_d2h(prog_h, prog_d, 32ull * n, s->d.stream) != 0 || igrt::event_record(L.ev, s->d.stream) != 0)
+        return IG_E_DEVICE;
+    for (u32 q : L.slots) {
+        s->inflight_n[q] += 1;
+        s->slot[q]->s_valid = false;
+        s->slot[q]->launches += 1;
+    }
+    L.busy = true;
+    s->next = (s->next + 1) % s->ring.size();
+    s->queued += 1;
+    *launched = true;
+    return IG_OK;
+}
+
+ig_status ig_server_poll(ig_server* s, uint32_t wait, ig_session_progress* out, size_t cap, size_t* n_out) {
+    if (!s || (!out && cap)) return IG_E_INVALID;
+    if (wait && s->queued && igrt::event_sync(s->ring[s->oldest].ev) != 0) return IG_E_DEVICE;
+    while (s->queued) {
+        const int q = igrt::event_query(s->ring[s->oldest].ev);
+        if (q < 0) return IG_E_DEVICE;
+        if (q == 0) break;
+        srv_collect(s);
+    }
+    while (s->queued < s->ring.size()) {
+        bool launched = false;
+        const ig_status st = srv_launch(s, &launched);
+        if (st != IG_OK) return st;
+        if (!launched) break;
+    }
+    size_t k = 0;
+    for (u32 q = 0; q < s->d.slots && k < cap; ++q) {
+        if (!s->slot[q]) continue;
+        ig_session_progress p = s->last[q];
+        p.slot = q;
+        p.in_flight = s->inflight_n[q] ? 1 : 0;
+        p.commands_recorded = (uint32_t)s->slot[q]->cmds.size();
+        out[k++] = p;
+    }
+    if (n_out) *n_out = k;
+    return IG_OK;
 }
 
 static ig_status refresh(ig_context* c) {

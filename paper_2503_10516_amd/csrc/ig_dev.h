@@ -361,6 +361,14 @@ int launch_pack_bindings(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n,
 int launch_pack_edges(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_edge* out_dev, void* stream);
 int launch_stats(const igd::DevCtx* dev_ctx, uint64_t n_instr, uint64_t n_bind, uint64_t n_edge,
                  igd::DevStats* out_dev, void* stream);
+// Events (completion of work queued on a stream) and a side stream.
+int event_create(void** ev);
+int event_record(void* ev, void* stream);
+int event_query(void* ev);  // 1 complete, 0 pending, -1 error
+int event_sync(void* ev);
+int event_destroy(void* ev);
+int stream_create(void** stream);  // non-blocking, default priority
+int stream_destroy(void* stream);
 // Device address of this GPU's fixed scratch array (IG_NOALLOC_SCRATCH_BYTES),
 // looked up once per device on first use; never allocates.
 int noalloc_scratch(void** out);

@@ -1974,7 +1974,7 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                             } else {
                                 src = live_containing_cell(c, b, pm, i0, i1, i2);
                                 if (src == 0) {
-                                    set_error(sh, IG_E_DEVICE);
+                                    set_error(sh, IG_E_INTERNAL);
                                 } else {
                                     const DAlloc& sa = c.allocs[src];
                                     l_pm = pm;
@@ -2029,7 +2029,7 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                         }
                 if (n == 0) continue;
                 const u32 dst = live_containing(c, b, m, r.lo, r.hi);
-                if (dst == 0) set_error(sh, IG_E_DEVICE);
+                if (dst == 0) set_error(sh, IG_E_INTERNAL);
                 const u64* gk;
                 const u32* gv;
                 if (big) {
@@ -2078,7 +2078,7 @@ IGD u64 stale_key(DevCtx& c, Shared& sh, SrcCache& l, u32 b, u32 pm, u32 p, u32 
           i2 < l.hi[2])) {
         const u32 src = live_containing_cell(c, b, pm, i0, i1, i2);
         if (src == 0) {
-            set_error(sh, IG_E_DEVICE);
+            set_error(sh, IG_E_INTERNAL);
             return 0;
         }
         const DAlloc& sa = c.allocs[src];
@@ -2202,7 +2202,7 @@ IGN void coherence_big(DevCtx& c, Shared& sh) {
                     while (ge < n && key2[ge] == key2[ge - 1]) ++ge;
                 }
                 dst = live_containing(c, b, m, r.lo, r.hi);
-                if (dst == 0) set_error(sh, IG_E_DEVICE);
+                if (dst == 0) set_error(sh, IG_E_INTERNAL);
                 cnt = emit_groups(c, sh, key2 + gs, val2 + gs, ge - gs, c.bufs[b], k, j, b, dst, m, 0, false);
             }
             const u32 excl2 = block_excl(sh, act ? cnt : 0, &tot);
@@ -2348,7 +2348,7 @@ IGN void kernels_emit_seq(DevCtx& c, Shared& sh, u32 kern_first) {
             for (u32 j = 0; j < A; ++j) {
                 const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
                 al[j] = rg.empty ? 0 : live_containing(c, rg.buffer, m, rg.lo, rg.hi);
-                if (!rg.empty && al[j] == 0) set_error(sh, IG_E_DEVICE);
+                if (!rg.empty && al[j] == 0) set_error(sh, IG_E_INTERNAL);
                 c.b_instr[bi + j] = x;
                 c.b_access[bi + j] = j;
                 c.b_alloc[bi + j] = al[j];
@@ -2492,7 +2492,7 @@ IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
             const Region& rk = kk == d * K ? rg : c.reg[kk * IG_MAX_ACCESS + j];
             const u32 al = live_containing(c, rk.buffer, m, rk.lo, rk.hi);
             if (!al) {
-                set_error(sh, IG_E_DEVICE);
+                set_error(sh, IG_E_INTERNAL);
                 continue;
             }
             const DAlloc& a = c.allocs[al];
@@ -2532,7 +2532,7 @@ IGN void kernels_emit_par(DevCtx& c, Shared& sh, u32 kern_first) {
         for (u32 j = 0; j < A; ++j) {
             const Region& rg = c.reg[k * IG_MAX_ACCESS + j];
             al[j] = rg.empty ? 0 : live_containing(c, rg.buffer, m, rg.lo, rg.hi);
-            if (!rg.empty && al[j] == 0) set_error(sh, IG_E_DEVICE);
+            if (!rg.empty && al[j] == 0) set_error(sh, IG_E_INTERNAL);
             c.b_instr[bi + j] = x;
             c.b_access[bi + j] = j;
             c.b_alloc[bi + j] = al[j];
@@ -2944,7 +2944,7 @@ IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
         refine_all(c, sh);
         if (failed(sh)) return;
         compute_regions(c, sh);
-        if (uniform(*c.miss_n) && tid() == 0) set_error(sh, IG_E_DEVICE);
+        if (uniform(*c.miss_n) && tid() == 0) set_error(sh, IG_E_INTERNAL);
         if (failed(sh)) return;
     }
     tick(c, sh, PH_INTAKE_REGIONS);
@@ -3141,7 +3141,7 @@ IGN void team_free(DevCtx& c, Shared& sh, bool act, u32 m, u32 g, u32 G, u32 ai,
         auto mark = [&](u32 id) {
             const u32 o = id - S;
             if (o >= R) {
-                set_error(sh, IG_E_DEVICE);
+                set_error(sh, IG_E_INTERNAL);
                 return;
             }
             atomicOr(&bm[o >> 6], 1ull << (o & 63));
@@ -3163,7 +3163,7 @@ IGN void team_free(DevCtx& c, Shared& sh, bool act, u32 m, u32 g, u32 G, u32 ai,
                 }
                 if (lo >= end) return;  // the whole run reads as S
                 if (end - S > R) {
-                    set_error(sh, IG_E_DEVICE);
+                    set_error(sh, IG_E_INTERNAL);
                     return;
                 }
                 // bits [lo - S, end - S), word by word
@@ -3654,6 +3654,32 @@ int graph_launch(void* exec, void* stream) {
     return check(hipGraphLaunch((hipGraphExec_t)exec, (hipStream_t)stream));
 }
 int graph_destroy(void* exec) { return check(hipGraphExecDestroy((hipGraphExec_t)exec)); }
+int event_create(void** ev) {
+    hipEvent_t e = nullptr;
+    if (check(hipEventCreateWithFlags(&e, hipEventDisableTiming))) return -1;
+    *ev = (void*)e;
+    return 0;
+}
+int event_record(void* ev, void* stream) { return check(hipEventRecord((hipEvent_t)ev, (hipStream_t)stream)); }
+int event_query(void* ev) {
+    const hipError_t e = hipEventQuery((hipEvent_t)ev);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    check(e);
+    return -1;
+}
+int event_sync(void* ev) { return check(hipEventSynchronize((hipEvent_t)ev)); }
+int event_destroy(void* ev) { return check(hipEventDestroy((hipEvent_t)ev)); }
+int stream_create(void** stream) {
+    hipStream_t st = nullptr;
+    if (check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking))) return -1;
+    *stream = (void*)st;
+    return 0;
+}
+int stream_destroy(void* stream) { return check(hipStreamDestroy((hipStream_t)stream)); }
 // The address of `scratch` on the current device, looked up on the first call
 // made with that device current and kept per device (each GPU has its own
 // copy of the array at its own address).

@@ -110,6 +110,26 @@ int launch_gather(DevCtx* const* ptrs, unsigned n, uint64_t* out, void*) {
     for (unsigned i = 0; i < n; ++i) gather_progress(*ptrs[i], (u64*)out + 4 * (size_t)i);
     return 0;
 }
+// Launches of the emulation complete synchronously: events are always done.
+int event_create(void** ev) {
+    *ev = std::malloc(1);
+    return *ev ? 0 : -1;
+}
+int event_record(void*, void*) { return 0; }
+int event_query(void*) { return 1; }
+int event_sync(void*) { return 0; }
+int event_destroy(void* ev) {
+    std::free(ev);
+    return 0;
+}
+int stream_create(void** stream) {
+    *stream = std::malloc(1);
+    return *stream ? 0 : -1;
+}
+int stream_destroy(void* stream) {
+    std::free(stream);
+    return 0;
+}
 // The emulation's stand-in for the fixed device array of the no-alloc calls.
 alignas(256) static unsigned char g_noalloc_scratch[IG_NOALLOC_SCRATCH_BYTES];
 int noalloc_scratch(void** out) {

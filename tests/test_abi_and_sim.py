@@ -218,6 +218,43 @@ def test_sim_serving_mix_equals_each_session_alone(sim_lib):
     assert out["p99_latency_us"] >= out["p50_latency_us"] > 0
 
 
+def test_sim_server_admission_busy_and_detach(sim_lib):
+    """ig_server_*: a full server answers IG_E_BUSY, as does one whose arena
+    budget a session would exceed; a session covered by a queued launch
+    cannot be detached; detached sessions equal the oracle."""
+    srv = B.Server(1, threads=64, lib_path=sim_lib)
+    a, b = S.stencil_1d(n=128, tasks=6), S.nbody_example()
+    sa = srv.admit(a, threads=64)
+    assert sa == 0 and srv.admit(b, threads=64) is None
+    ca = srv.context(sa)
+    for c in a.cmds:
+        ca.record_command(c)
+    prog = srv.poll()
+    assert len(prog) == 1 and prog[0].slot == 0 and prog[0].in_flight == 1
+    assert srv.detach(sa) is None  # the queued launch still covers it
+    prog = srv.poll()
+    assert prog[0].in_flight == 0 and prog[0].finished == 1 and prog[0].tasks_done == a.n_tasks
+    assert prog[0].commands_done == prog[0].commands_recorded == len(a.cmds)
+    da = srv.detach(sa)
+    assert da is not None and srv.poll() == []
+    assert_same(oracle.run_stream(a), da.fetch_all(), "server:" + a.name)
+    da.close()
+    sb = srv.admit(b, threads=64)  # the slot is free again
+    assert sb == 0
+    srv.close()
+    # budget: one arena fits, a second does not
+    one = B.Server(4, threads=64, lib_path=sim_lib)
+    import ctypes as ct
+    d, _, _ = B.context_desc(one.L, "host", None, threads=64, **a.desc(), **B.estimate_caps(a))
+    need = ct.c_uint64()
+    assert one.L.ig_arena_bytes(ct.byref(d), ct.byref(need)) == 0
+    one.close()
+    srv = B.Server(4, threads=64, arena_budget=int(need.value * 1.5), lib_path=sim_lib)
+    assert srv.admit(a, threads=64, **B.estimate_caps(a)) is not None
+    assert srv.admit(a, threads=64, **B.estimate_caps(a)) is None
+    srv.close()
+
+
 @pytest.mark.parametrize("variant", range(4))
 def test_sim_reader_runs(variant, sim_lib):
     s = reader_run_stream(variant)
