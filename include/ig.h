@@ -437,6 +437,10 @@ ig_status ig_stats_get(ig_context* ctx, ig_stats* out);
 
 const char* ig_status_str(ig_status st);
 
+/* The message of the last HIP runtime error this thread's calls saw (the
+ * cause of an IG_E_DEVICE); "" if none.  Owned by the library. */
+const char* ig_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

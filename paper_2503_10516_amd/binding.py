@@ -32,7 +32,13 @@ IG_E_INTERNAL = -6
 
 class IgError(RuntimeError):
     def __init__(self, where: str, status: int):
-        super().__init__(f"{where} failed: {status}")
+        detail = ""
+        if status == IG_E_DEVICE:
+            try:
+                detail = " (" + lib().ig_last_error().decode(errors="replace") + ")"
+            except Exception:
+                pass
+        super().__init__(f"{where} failed: {status}{detail}")
         self.status = status
 
 
@@ -84,7 +90,7 @@ EXPORTS = [
     "ig_fetch_task_times", "ig_stats_get", "ig_status_str", "ig_batch_rewind", "ig_batch_progress",
     "ig_batch_graph_create", "ig_graph_launch", "ig_graph_destroy", "ig_batch_flush_window",
     "ig_batch_progress_noalloc", "ig_server_create", "ig_server_destroy", "ig_server_admit", "ig_server_session",
-    "ig_server_submit", "ig_server_poll", "ig_server_detach",
+    "ig_server_submit", "ig_server_poll", "ig_server_detach", "ig_last_error",
 ]
 
 _libs: Dict[str, ctypes.CDLL] = {}
@@ -132,6 +138,8 @@ def lib(path: Optional[str] = None) -> ctypes.CDLL:
     L.ig_fetch_task_times.argtypes = [vp, P(ctypes.c_double), ctypes.c_size_t, P(ctypes.c_size_t)]
     L.ig_stats_get.argtypes = [vp, P(Stats)]
     L.ig_status_str.argtypes = [ctypes.c_int32]
+    L.ig_last_error.argtypes = []
+    L.ig_last_error.restype = ctypes.c_char_p
     L.ig_status_str.restype = ctypes.c_char_p
     for n in EXPORTS:
         if n != "ig_status_str":

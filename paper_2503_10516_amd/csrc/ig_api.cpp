@@ -250,6 +250,8 @@ const char* ig_status_str(ig_status st) {
     }
 }
 
+const char* ig_last_error(void) { return igrt::last_error(); }
+
 ig_status ig_arena_bytes(const ig_context_desc* desc, uint64_t* bytes) {
     Caps k;
     if (!make_caps(desc, k) || !bytes) return IG_E_INVALID;

@@ -1148,31 +1148,29 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
         if (!iv) atomicAdd(&B.uninit, 1u);
         W64(c, B.stamp_off)[cell] = W64(c, sh.scan_tmp[5])[oc];
     }
-    // --- allocation maps: each by the owner of its memory ---
+    // --- allocation maps: every thread takes cells of every allocation
+    // (each new cell comes from one old cell; reader blocks come from the
+    // memory's free list, which any thread may use) ---
     const u32 na = sh.scan_tmp[9];
     for (u32 s = 0; s < na; ++s) {
         const u32 id = c.cons_off[s];
-        DAlloc& a = c.allocs[id];
-        if (owner_of(a.mem) != tid()) continue;
+        const DAlloc& a = c.allocs[id];
         const Region& sv = c.reg[s];
         const u32 on1a = sv.chi[1] - sv.clo[1], on2a = sv.chi[2] - sv.clo[2];
+        const u32 n1 = a.chi[1] - a.clo[1], n2 = a.chi[2] - a.clo[2];
         AmCell* cells = am_cells(c, a);
-        AmCell* ocl = (AmCell*)(c.heap + sv.buffer);
+        const AmCell* ocl = (const AmCell*)(c.heap + sv.buffer);
         // Refinement only splits cells: the first new cell of an old cell
         // takes over its reader list, the other parts get copies.
-        u32 l = 0;
-        for (u32 i0 = a.clo[0]; i0 < a.chi[0]; ++i0) {
+        for (u32 l = tid(); l < a.ncells; l += nt()) {
+            const u32 i2 = a.clo[2] + l % n2, i1 = a.clo[1] + (l / n2) % n1, i0 = a.clo[0] + l / (n1 * n2);
             const bool f0 = i0 == a.clo[0] || r0[i0 - 1] != r0[i0];
-            for (u32 i1 = a.clo[1]; i1 < a.chi[1]; ++i1) {
-                const bool f1 = i1 == a.clo[1] || r1[i1 - 1] != r1[i1];
-                for (u32 i2 = a.clo[2]; i2 < a.chi[2]; ++i2, ++l) {
-                    const bool f2 = i2 == a.clo[2] || r2[i2 - 1] != r2[i2];
-                    const u32 ol = ((r0[i0] - sv.clo[0]) * on1a + (r1[i1] - sv.clo[1])) * on2a + (r2[i2] - sv.clo[2]);
-                    AmCell e = am_load(ocl + ol);
-                    if (!(f0 && f1 && f2) && e.ov) e.ov = rd_copy(c, sh, a.mem, e.ov);
-                    cells[l] = e;
-                }
-            }
+            const bool f1 = i1 == a.clo[1] || r1[i1 - 1] != r1[i1];
+            const bool f2 = i2 == a.clo[2] || r2[i2 - 1] != r2[i2];
+            const u32 ol = ((r0[i0] - sv.clo[0]) * on1a + (r1[i1] - sv.clo[1])) * on2a + (r2[i2] - sv.clo[2]);
+            AmCell e = am_load(ocl + ol);
+            if (!(f0 && f1 && f2) && e.ov) e.ov = rd_copy(c, sh, a.mem, e.ov);
+            cells[l] = e;
         }
     }
     bar();
@@ -1592,6 +1590,8 @@ IGD void live_remove(DevCtx& c, u32 b, u32 m, u32 id) {
         }
 }
 
+IGN void free_stage_one(DevCtx& c, Shared& sh, u32 x, const DAlloc& a, u64* bm);
+
 IGN void alloc_phase(DevCtx& c, Shared& sh) {
     const u32 NP = sh.s.n_buffers * c.n_mem, A = sh.t_nacc, C = c.chunks;
     for (u32 i = tid(); i < NP; i += nt()) {
@@ -1725,10 +1725,7 @@ IGN void alloc_phase(DevCtx& c, Shared& sh) {
                     DAlloc& old = c.allocs[absorb[q]];
                     const u32 xf = x++;
                     put_instr(c, xf, IG_FREE, 0, sh.t_id, NONE, b, m, 0xFFFF, absorb[q], 0, old.lo, old.hi);
-                    SrcSet s;
-                        ss_init(c, s);
-                    free_edges(c, sh, s, old);
-                    stage(c, sh, xf, s);
+                    free_stage_one(c, sh, xf, old, c.wk_key + (size_t)tid() * c.cap_scr);
                     release_readers(c, old);
                     old.alive = 0;
                     live_remove(c, b, m, absorb[q]);
@@ -3107,6 +3104,102 @@ IGN void create_buffer(DevCtx& c, Shared& sh, const DevCmd& cmd) {
 }
 
 // Sec. 3.2: a destroyed buffer's device allocations are freed (ascending id)
+// Mark the LIFETIME sources one allocation-map cell gives a FREE (its writer
+// and readers after substitution) in a bitmap over ids [S, S + R); with
+// `shared` the bitmap is marked by several threads at once.
+IGD void free_mark_cell(DevCtx& c, Shared& sh, const AmCell& e, u32 R, u64* bm, bool shared) {
+    const u32 S = sh.s.S, E = sh.s.E;
+    auto mark = [&](u32 id) {
+        const u32 o = id - S;
+        if (o >= R) {
+            set_error(sh, IG_E_INTERNAL);
+            return;
+        }
+        if (shared)
+            atomicOr(&bm[o >> 6], 1ull << (o & 63));
+        else
+            bm[o >> 6] |= 1ull << (o & 63);
+    };
+    const u32 wr = e.w & ~W_ALLOC;
+    mark(wr < S ? S : wr);
+    u32 r;
+    if (e.r0 != NONE && eff_r(sh, e.r0, r)) mark(r);
+    if (e.r1 != NONE && eff_r(sh, e.r1, r)) mark(r);
+    rd_each(c, e.ov, [&](u32 first, u32 n) {
+        const u32 end = first + n;
+        u32 lo = first < E ? E : first;
+        if (lo >= end) return;
+        if (lo < S) {
+            mark(S);
+            lo = S;
+        }
+        if (lo >= end) return;  // the whole run reads as S
+        if (end - S > R) {
+            set_error(sh, IG_E_INTERNAL);
+            return;
+        }
+        // bits [lo - S, end - S), word by word
+        for (u32 o = lo - S; o < end - S;) {
+            const u32 wd = o >> 6, b0 = o & 63;
+            const u32 b1 = (end - S) - (wd << 6) < 64 ? (end - S) - (wd << 6) : 64;
+            const u64 mk = (b1 == 64 ? ~0ull : ((1ull << b1) - 1)) & ~((1ull << b0) - 1);
+            if (shared)
+                atomicOr(&bm[wd], mk);
+            else
+                bm[wd] |= mk;
+            o = (wd << 6) + b1;
+        }
+    });
+}
+
+// FREE x of allocation a by one thread (the allocation phase): its sources
+// from a bitmap over [S, x) in the thread's scratch, staged in id order;
+// a range beyond the bitmap's size uses a sorted source list instead.
+IGN void free_stage_one(DevCtx& c, Shared& sh, u32 x, const DAlloc& a, u64* bm) {
+    const u32 S = sh.s.S, R = x - S;
+    if ((u64)R > 64ull * c.cap_scr) {
+        SrcSet s;
+        ss_init(c, s);
+        free_edges(c, sh, s, a);
+        stage(c, sh, x, s);
+        return;
+    }
+    const u32 words = (R + 63) / 64;
+    for (u32 i = 0; i < words; ++i) bm[i] = 0;
+    const AmCell* cl = am_cells(c, a);
+    for (u32 l = 0; l < a.ncells; ++l) free_mark_cell(c, sh, am_load(cl + l), R, bm, false);
+    u32 n = 0;
+    for (u32 i = 0; i < words; ++i) n += __popcll(bm[i]);
+    const u32 slot = x - sh.unit_first;
+    const u32 cnt = n ? n : 1;
+    const u32 off = atomicAdd(&sh.stage_top, cnt);
+    if ((u64)off + cnt > (u64)c.cap_unit * 8 || slot >= c.cap_unit) {
+        cap_error(sh, IG_CAP_UNIT);
+        return;
+    }
+    c.tab_off[slot] = off;
+    c.tab_cnt[slot] = cnt;
+    if (n == 0) {  // no dependency: wait for the synchronisation point
+        c.stage_from[off] = S;
+        c.stage_kind[off] = IG_DEP_SYNC;
+        c.has_succ[S] = 1;
+        return;
+    }
+    u32 o = off;
+    for (u32 i = 0; i < words; ++i) {
+        u64 v = bm[i];
+        while (v) {
+            const u32 bit = __ffsll((long long)v) - 1;
+            v &= v - 1;
+            const u32 from = S + (i << 6) + bit;
+            c.stage_from[o] = from;
+            c.stage_kind[o] = IG_DEP_LIFETIME;
+            c.has_succ[from] = 1;
+            ++o;
+        }
+    }
+}
+
 // The FREE x of allocation a (Sec. 3.2), its edges found by the team of its
 // memory: every writer and reader of the allocation, after substitution,
 // lies in [S, x), so the members mark them in a bitmap of that range (one
@@ -3138,44 +3231,7 @@ IGN void team_free(DevCtx& c, Shared& sh, bool act, u32 m, u32 g, u32 G, u32 ai,
     const u32 l1 = act && l0 + per < a.ncells ? l0 + per : (act ? a.ncells : 0);
     if (bits) {
         const AmCell* cl = am_cells(c, a);
-        auto mark = [&](u32 id) {
-            const u32 o = id - S;
-            if (o >= R) {
-                set_error(sh, IG_E_INTERNAL);
-                return;
-            }
-            atomicOr(&bm[o >> 6], 1ull << (o & 63));
-        };
-        for (u32 l = l0; l < l1; ++l) {
-            const AmCell e = am_load(cl + l);
-            const u32 wr = e.w & ~W_ALLOC;
-            mark(wr < S ? S : wr);
-            u32 r;
-            if (e.r0 != NONE && eff_r(sh, e.r0, r)) mark(r);
-            if (e.r1 != NONE && eff_r(sh, e.r1, r)) mark(r);
-            rd_each(c, e.ov, [&](u32 first, u32 n) {
-                const u32 end = first + n;
-                u32 lo = first < E ? E : first;
-                if (lo >= end) return;
-                if (lo < S) {
-                    mark(S);
-                    lo = S;
-                }
-                if (lo >= end) return;  // the whole run reads as S
-                if (end - S > R) {
-                    set_error(sh, IG_E_INTERNAL);
-                    return;
-                }
-                // bits [lo - S, end - S), word by word
-                for (u32 o = lo - S; o < end - S;) {
-                    const u32 wd = o >> 6, b0 = o & 63;
-                    const u32 b1 = (end - S) - (wd << 6) < 64 ? (end - S) - (wd << 6) : 64;
-                    const u64 mk = (b1 == 64 ? ~0ull : ((1ull << b1) - 1)) & ~((1ull << b0) - 1);
-                    atomicOr(&bm[wd], mk);
-                    o = (wd << 6) + b1;
-                }
-            });
-        }
+        for (u32 l = l0; l < l1; ++l) free_mark_cell(c, sh, am_load(cl + l), R, bm, true);
     }
     bar();
     // set bits -> staged edges, in order
