@@ -220,15 +220,21 @@ typedef struct ig_stats {
 
 typedef struct ig_context ig_context;
 
-/* Device memory a descriptor needs (arena size).  Errors: IG_E_INVALID. */
+/* Device memory a descriptor needs (arena size): the command log, the
+ * output records and the region maps of the simulated cluster (Sec. 3.2:
+ * memories and allocations as numeric ids).  Errors: IG_E_INVALID. */
 ig_status ig_arena_bytes(const ig_context_desc* desc, uint64_t* bytes);
 
-/* Create a context: validates the cluster shape, prepares device state and
- * records the initial epoch I0.  Errors: IG_E_INVALID, IG_E_CAPACITY (arena
- * too small), IG_E_DEVICE. */
+/* Create a context: one user program on a simulated cluster of nodes x
+ * devices (Sec. 3.1), memory M0 the user's host memory, M1 pinned host
+ * memory and M2.. the devices (Sec. 3.2).  Validates the cluster shape,
+ * prepares device state and records the initial epoch I0 (Sec. 2.4,
+ * Table 1).  Errors: IG_E_INVALID, IG_E_CAPACITY (arena too small),
+ * IG_E_DEVICE. */
 ig_status ig_context_create(const ig_context_desc* desc, ig_context** out);
 
-/* Destroy: waits for outstanding work; frees library-owned memory. */
+/* Destroy: waits for outstanding work on the context's stream; frees
+ * library-owned memory.  (The program's end is ig_shutdown, Sec. 3.2.) */
 ig_status ig_context_destroy(ig_context* ctx);
 
 /* Record a buffer (ids 0, 1, ... in creation order).  IG_INIT_HOST buffers
@@ -253,16 +259,19 @@ ig_status ig_submit_tasks(ig_context* ctx, const ig_task_desc* tasks, size_t n, 
 /* Record a user epoch: flush the queue, then synchronise (Table 1). */
 ig_status ig_epoch(ig_context* ctx);
 
-/* Record shutdown: destroy every remaining buffer, then the final epoch.
- * No command may follow. */
+/* Record shutdown: destroy every remaining buffer (their allocations are
+ * freed, Sec. 3.2), then the final epoch (Table 1).  No command may follow. */
 ig_status ig_shutdown(ig_context* ctx);
 
-/* Analyse everything recorded so far (asynchronously on the stream).  Does
- * not force a lookahead flush: output never depends on timing. */
+/* Analyse everything recorded so far (asynchronously on the stream):
+ * commands enter the lookahead queue or are compiled into instructions
+ * (Sec. 3, Sec. 4.3).  Does not force a lookahead flush: output never
+ * depends on timing. */
 ig_status ig_flush_window(ig_context* ctx);
 
 /* Analyse the pending windows of n contexts in ONE launch (one workgroup
- * per context; all must use the same `threads`).  stream: NULL = the first
+ * per context; all must use the same `threads`); each context's graph is
+ * the one ig_flush_window gives (Sec. 3).  stream: NULL = the first
  * context's stream. */
 ig_status ig_batch_flush(ig_context* const* ctxs, size_t n, void* stream);
 
@@ -403,18 +412,26 @@ ig_status ig_server_poll(ig_server* srv, uint32_t wait, ig_session_progress* out
  * queued launch covers it.  Errors: IG_E_INVALID. */
 ig_status ig_server_detach(ig_server* srv, uint32_t slot, ig_context** out);
 
-/* Wait for the context's outstanding work; reports IG_E_CAPACITY or
- * IG_E_DEVICE raised during analysis. */
+/* Wait for the context's outstanding work; reports IG_E_CAPACITY,
+ * IG_E_INTERNAL or IG_E_DEVICE raised during analysis.  (A host-side wait;
+ * the program-level synchronisation is ig_epoch, Sec. 2.4.) */
 ig_status ig_sync(ig_context* ctx);
 
 /* Forget all analysis results (the recorded commands stay); the next flush
- * re-analyses the stream from the start.  Used to re-run a recorded stream. */
+ * re-analyses the stream from the start, giving the same graph (the
+ * analysis is a function of the command stream, Sec. 3).  Used to re-run a
+ * recorded stream. */
 ig_status ig_rewind(ig_context* ctx);
 
-/* Counts of records produced so far (after ig_sync). */
+/* Counts of the IDAG records produced so far (Sec. 3.6): instructions,
+ * kernel bindings, edges, and tasks analysed (after ig_sync). */
 ig_status ig_counts(ig_context* ctx, uint64_t* n_instr, uint64_t* n_bind, uint64_t* n_edge, uint64_t* n_tasks);
 
-/* Copy records into host arrays, continuing from the previous fetch. */
+/* Copy records into host arrays, continuing from the previous fetch:
+ * instructions in id order, which is a topological order (Sec. 4.1), of the
+ * kinds of Table 1 used here; kernel bindings by (instruction, access); edges
+ * by (to, from) with the dependency kinds of the IDAG figure's legend
+ * (Sec. 3.6); per-task statuses of the Sec. 4.4 checks. */
 ig_status ig_fetch_instructions(ig_context* ctx, ig_instruction* dst, size_t cap, size_t* n_out);
 ig_status ig_fetch_bindings(ig_context* ctx, ig_binding* dst, size_t cap, size_t* n_out);
 ig_status ig_fetch_edges(ig_context* ctx, ig_edge* dst, size_t cap, size_t* n_out);
@@ -431,8 +448,9 @@ ig_status ig_fetch_task_status(ig_context* ctx, int32_t* dst, size_t cap, size_t
  * rejected task has all of the last three equal.  cap = tasks. */
 ig_status ig_fetch_task_times(ig_context* ctx, double* dst, size_t cap, size_t* n_out);
 
-/* Per-kind counts, resizes, warnings and the three record digests, all
- * computed on the device. */
+/* Per-kind counts (Table 1), per-dependency-kind counts (Sec. 3.6),
+ * resizes (Sec. 3.2, 4.3), warnings (Sec. 4.4) and the three record
+ * digests, all computed on the device. */
 ig_status ig_stats_get(ig_context* ctx, ig_stats* out);
 
 const char* ig_status_str(ig_status st);
