@@ -349,6 +349,43 @@ def run_single(name, stream, golden_name, steps, threads, copy_gbs, oracle_reps)
     return out
 
 
+def run_task_graph_horizons(threads):
+    """Horizons from the task graph (horizon mode 1) on a few streams: the
+    2-D stencil (a chain: the same graph as the fixed step) and three
+    batched streams (fewer horizons where tasks run side by side), each
+    analysed on the GPU and compared with the oracle run here."""
+    import torch
+    import oracle
+    from paper_2503_10516_amd import binding, streams
+    cases = [("stencil2d", streams.stencil_2d())] + \
+        [(f"batched_{i}", streams.batched_stream(streams.BATCHED_SEED, i, w_all=streams.BATCHED_W_ALL,
+                                                 w_slice=streams.BATCHED_W_SLICE)) for i in (0, 5, 12)]
+    out = []
+    for name, s in cases:
+        row = {"stream": name}
+        for mode in (0, 1):
+            s.horizon_mode = mode
+            ctx = binding.make_context(s, threads=threads)
+            ctx.record(s)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.flush()
+            assert ctx.sync() == 0
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            st = ctx.stats()
+            ctx.close()
+            ref = oracle.run_stream(s, fetch=False)["stats"]
+            row[f"mode{mode}"] = {"gpu_ms": dt * 1e3, "horizons": st["per_kind"][5],
+                                  "records": st["n_instructions"] + st["n_edges"],
+                                  "oracle_equal": all(st[k] == ref[k] for k in DIGEST_KEYS)}
+        s.horizon_mode = 0
+        out.append(row)
+        log(f"task-graph horizons {name}: {row['mode0']['horizons']} -> {row['mode1']['horizons']} horizons, "
+            f"oracle equal {row['mode1']['oracle_equal']}")
+    return out
+
+
 def run_serving(args):
     from paper_2503_10516_amd import serve, streams
     sessions = streams.serving_sessions(n_sessions=args.serving_sessions)
@@ -378,8 +415,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--threads", type=int, default=256, help="workgroup size of the single-stream objects")
-    ap.add_argument("--workloads", default="stencil2d,nbody,stencil1d,serving",
-                    help="comma list of objects beside the batched headline: stencil2d, nbody, stencil1d, serving")
+    ap.add_argument("--workloads", default="stencil2d,nbody,stencil1d,tdag,serving",
+                    help="comma list of objects beside the batched headline: stencil2d, nbody, stencil1d, tdag "
+                         "(horizons from the task graph), serving")
     ap.add_argument("--batch-threads", type=int, default=0, help="0: autotune")
     ap.add_argument("--batch-window", type=int, default=400, help="commands per launch while sizing")
     ap.add_argument("--serving-rates", default="1e3,1e5")
@@ -459,6 +497,8 @@ def main():
         line["stencil1d"] = run_single("1-D 3-point stencil: 2 buffers of 4096, 64 tasks, 2 devices",
                                        streams.stencil_1d(), "stencil1d_full.json", max(args.steps, 10),
                                        args.threads, copy_gbs, 10)
+    if "tdag" in work:
+        line["task_graph_horizons"] = run_task_graph_horizons(args.threads)
     if "serving" in work:
         line["serving"] = run_serving(args)
     print(json.dumps(line))

@@ -149,6 +149,10 @@ typedef struct ig_context_desc {
     uint32_t flush_horizons;    /* horizons after the last allocating command before a flush (0: 2) */
     uint32_t queue_cap;         /* flush when the queue holds this many commands (0: unbounded) */
     uint32_t threads;           /* workgroup size of this stream's analysis (0: 256); tuning only */
+    uint32_t horizon_mode;      /* Sec. 3.5: 0 a horizon every horizon_step accepted tasks; 1 from the
+                                   task graph: when its critical-path length has grown by horizon_step
+                                   since the last horizon or epoch, or horizon_max_tasks tasks came since */
+    uint32_t horizon_max_tasks; /* horizon_mode 1: tasks between horizons at most (0: 16 x horizon_step) */
     uint64_t cap_commands;      /* recorded commands (0: 65536) */
     uint64_t cap_instructions;  /* output instructions (0: 1<<20) */
     uint64_t cap_edges;         /* output edges (0: 4 * cap_instructions) */

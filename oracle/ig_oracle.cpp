@@ -409,6 +409,15 @@ struct AllocEntry {  // one piece of an allocation-level map
     std::vector<uint32_t> readers;  // sorted, unique
 };
 
+// One piece of a buffer's task-level map (Sec. 3.5 horizons from the task
+// graph): the critical-path length of the element's last writer task and the
+// largest one among the tasks that read it since (0 or at most the last
+// epoch's: no reader).
+struct CpEntry {
+    Box box;
+    uint32_t wcp, rcp;
+};
+
 struct Buffer {
     uint32_t dims;
     int64_t ext[3];
@@ -418,6 +427,7 @@ struct Buffer {
     uint32_t user_alloc;
     std::vector<BufEntry> map;
     std::vector<Box> initialised;  // disjoint boxes
+    std::vector<CpEntry> cp_map;   // task-level map (horizon_mode 1)
     Box whole() const {
         int64_t lo[3] = {0, 0, 0};
         return make_box(lo, ext);
@@ -472,6 +482,12 @@ struct Sources {  // incoming edges of one instruction, kinds OR-ed per source
 
 struct igo_context {
     uint32_t nodes, devices, chunks, per_dev, horizon_step, lookahead, flush_horizons, queue_cap;
+    uint32_t horizon_mode = 0, horizon_max_tasks = 0;
+    // task graph (horizon_mode 1): critical-path lengths of the task-level
+    // synchronisation point (latest epoch or applied horizon), of the latest
+    // epoch, of the generated horizon not yet applied (0: none), the longest
+    // path so far and its length when the last horizon or epoch came
+    uint32_t cp_sync = 0, cp_epoch = 0, cp_pending = 0, cp_max = 0, cp_last = 0;
     std::vector<Buffer> buffers;
     std::vector<Alloc> allocs;  // index = allocation id; [0] unused
     std::map<std::pair<uint32_t, uint16_t>, std::vector<uint32_t>> live;
@@ -980,6 +996,61 @@ struct igo_context {
         sync_point = ei;
         pending_horizon = NONE;
         tasks_since_sync = 0;
+        // the task graph: the epoch follows everything so far
+        cp_epoch = cp_sync = cp_max = cp_last = cp_max + 1;
+        cp_pending = 0;
+    }
+
+    // ----- Sec. 3.5: the task graph behind horizon_mode 1 -----
+    // Critical-path length of an accepted task: one more than the longest of
+    // the sync point and the tasks it depends on.  Per buffer element, over
+    // the whole task's regions (every chunk; reads see the state before the
+    // task): a read depends on the last writer; a write on the readers since
+    // the last write, else on the last writer.  Tasks before the sync point
+    // read as it (the compaction of horizons and epochs).
+    uint32_t task_cp(const TaskCmd& t) {
+        auto eff = [&](uint32_t v) { return v < cp_sync ? cp_sync : v; };
+        uint32_t d = cp_sync;
+        for (const auto& regs : t.regions)
+            for (const Region& rg : regs) {
+                if (is_empty(rg.box)) continue;
+                for (const CpEntry& e : buffers[rg.buffer].cp_map) {
+                    if (!intersects(e.box, rg.box)) continue;
+                    if (rg.mode & IGO_READ) d = std::max(d, eff(e.wcp));
+                    if (rg.mode & IGO_WRITE) d = std::max(d, e.rcp > cp_epoch ? eff(e.rcp) : eff(e.wcp));
+                }
+            }
+        return d + 1;
+    }
+
+    // Record task t (critical-path length cp) in the task-level maps: reads
+    // first, then writes (an element the task both reads and writes ends
+    // written, with no reader).
+    void task_cp_apply(const TaskCmd& t, uint32_t cp) {
+        for (int pass = 0; pass < 2; ++pass)
+            for (const auto& regs : t.regions)
+                for (const Region& rg : regs) {
+                    if (is_empty(rg.box)) continue;
+                    if (pass == 0 && !(rg.mode & IGO_READ)) continue;
+                    if (pass == 1 && !(rg.mode & IGO_WRITE)) continue;
+                    std::vector<CpEntry> out;
+                    for (const CpEntry& e : buffers[rg.buffer].cp_map) {
+                        if (!intersects(e.box, rg.box)) {
+                            out.push_back(e);
+                            continue;
+                        }
+                        for (const Box& p : subtract(e.box, rg.box)) out.push_back(CpEntry{p, e.wcp, e.rcp});
+                        CpEntry in{intersect(e.box, rg.box), e.wcp, e.rcp};
+                        if (pass == 0) {
+                            in.rcp = std::max(in.rcp > cp_epoch ? in.rcp : 0u, cp);
+                        } else {
+                            in.wcp = cp;
+                            in.rcp = 0;
+                        }
+                        out.push_back(in);
+                    }
+                    buffers[rg.buffer].cp_map.swap(out);
+                }
     }
 
     void destroy_buffer(uint32_t b) {
@@ -1031,7 +1102,7 @@ int32_t igo_context_create(const igo_context_desc* d, igo_context** out) {
     const uint32_t devs = d->nodes * d->devices_per_node;
     const uint32_t chunks = d->chunks ? d->chunks : devs;
     if (chunks % devs != 0 || chunks > 65536) return IGO_E_INVALID;
-    if (d->lookahead > 1) return IGO_E_INVALID;
+    if (d->lookahead > 1 || d->horizon_mode > 1) return IGO_E_INVALID;
     igo_context* c = new igo_context();
     c->nodes = d->nodes;
     c->devices = d->devices_per_node;
@@ -1041,6 +1112,8 @@ int32_t igo_context_create(const igo_context_desc* d, igo_context** out) {
     c->lookahead = d->lookahead;
     c->flush_horizons = d->flush_horizons ? d->flush_horizons : 2;
     c->queue_cap = d->queue_cap;
+    c->horizon_mode = d->horizon_mode;
+    c->horizon_max_tasks = d->horizon_max_tasks ? d->horizon_max_tasks : 16 * c->horizon_step;
     c->allocs.push_back(Alloc{0, 0, 0, Box{{0, 0, 0}, {0, 0, 0}}, false, {}});
     // the initial epoch I0
     c->emit(IGO_EPOCH, 0, NONE, NONE, NONE, NONE16, NONE16, 0, 0, Box{{0, 0, 0}, {0, 0, 0}});
@@ -1103,6 +1176,7 @@ int32_t igo_buffer_create(igo_context* c, uint32_t dims, const int64_t extent[3]
         e.pm = NONE16;
     }
     b.map.push_back(e);
+    b.cp_map.push_back(CpEntry{b.whole(), 0, 0});
     c->buffers.push_back(b);
     if (out_buffer) *out_buffer = id;
     return IGO_OK;
@@ -1197,7 +1271,24 @@ int32_t igo_submit_task(igo_context* c, const igo_task_desc* td, uint64_t* out_t
     cmd.task = t;
     cmd.event = c->begin_event(IGO_EV_TASK, t.id);
     c->push_command(cmd);
-    if (++c->tasks_since_sync == c->horizon_step) {
+    // Sec. 3.5: is a horizon due after this task?
+    bool horizon;
+    if (c->horizon_mode == 1) {
+        const uint32_t cp = c->task_cp(t);
+        c->task_cp_apply(t, cp);
+        c->cp_max = std::max(c->cp_max, cp);
+        horizon = c->cp_max - c->cp_last >= c->horizon_step || ++c->tasks_since_sync >= c->horizon_max_tasks;
+        if (horizon) {
+            // the horizon follows the whole front; the one before it becomes
+            // the task-level synchronisation point
+            if (c->cp_pending) c->cp_sync = c->cp_pending;
+            c->cp_pending = c->cp_max + 1;
+            c->cp_last = c->cp_max;
+        }
+    } else {
+        horizon = ++c->tasks_since_sync == c->horizon_step;
+    }
+    if (horizon) {
         c->tasks_since_sync = 0;
         Cmd h;
         h.horizon = true;

@@ -97,6 +97,14 @@ typedef struct igo_context_desc {
     uint32_t lookahead;       /* 0 off, 1 on */
     uint32_t flush_horizons;  /* 0: 2 */
     uint32_t queue_cap;       /* 0: unbounded */
+    /* Sec. 3.5: when a horizon enters the command stream.  0: after every
+     * horizon_step accepted tasks since the last horizon or epoch.  1: from
+     * the task graph -- when its critical-path length has grown by
+     * horizon_step since the last horizon or epoch, or when
+     * horizon_max_tasks tasks have been accepted since then (0: 16 x
+     * horizon_step), whichever comes first. */
+    uint32_t horizon_mode;
+    uint32_t horizon_max_tasks;
     uint32_t pad;
 } igo_context_desc;
 

@@ -14,6 +14,7 @@ using namespace igd;
 struct Caps {
     u32 nodes, devices, chunks, per_dev, n_dev, n_mem, mw;
     u32 horizon_step, lookahead, flush_horizons, queue_cap, threads, n_workers;
+    u32 horizon_mode, horizon_max_tasks;
     u32 cap_cmds, cap_allocs, cap_queue, cap_heap, cap_rb, cap_unit, cap_scr, cap_src, cap_box;
     u64 cap_instr, cap_edges, cap_binds;
     u64 pack_bytes;
@@ -63,6 +64,9 @@ static bool make_caps(const ig_context_desc* d, Caps& k) {
     k.lookahead = d->lookahead;
     k.flush_horizons = d->flush_horizons ? d->flush_horizons : 2;
     k.queue_cap = d->queue_cap;
+    if (d->horizon_mode > 1) return false;
+    k.horizon_mode = d->horizon_mode;
+    k.horizon_max_tasks = d->horizon_max_tasks ? d->horizon_max_tasks : 16 * k.horizon_step;
     k.threads = d->threads ? d->threads : 256;
     if (k.threads < 64 || k.threads > MAX_THREADS || (k.threads & 63)) return false;
     k.n_workers = std::min(k.threads, k.n_mem);
@@ -201,6 +205,8 @@ static void fill_config(const Caps& k, DevCtx& h) {
     h.queue_cap = k.queue_cap;
     h.threads = k.threads;
     h.n_workers = k.n_workers;
+    h.horizon_mode = k.horizon_mode;
+    h.horizon_max_tasks = k.horizon_max_tasks;
     h.cap_cmds = k.cap_cmds;
     h.cap_allocs = k.cap_allocs;
     h.cap_queue = k.cap_queue;

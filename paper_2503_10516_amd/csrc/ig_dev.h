@@ -160,6 +160,8 @@ struct DBuf {
     u32 init_off;   // u32[ncells]   initialised (Sec. 4.4)
     u32 uninit;     // cells not yet initialised (0: the whole buffer is)
     u32 stamp_off;  // u64[ncells]   overlapping-write detection: (task+1)<<32 | chunk
+    u32 wcp_off;    // u32[ncells]   task graph (horizon mode 1): critical-path length of the last writer task
+    u32 rcp_off;    // u32[ncells]   the longest among the reader tasks since (<= cp_epoch: none)
 };
 
 struct DAlloc {
@@ -228,6 +230,11 @@ struct Scalars {
     i32 error;
     u32 done_tasks;      // leading tasks whose records are complete (none held in the queue)
     u32 cap_what;        // with IG_E_CAPACITY: which capacity (IG_CAP_*)
+    // task graph (horizon mode 1): critical-path lengths of the task-level
+    // sync point (latest epoch or applied horizon), of the latest epoch, of
+    // the generated horizon not yet applied (0: none), the longest path so
+    // far and its length at the last horizon or epoch
+    u32 cp_sync, cp_epoch, cp_pending, cp_max, cp_last;
     u32 pad;
 };
 
@@ -236,6 +243,7 @@ struct DevCtx {
     u32 nodes, devices, chunks, per_dev, n_dev, n_mem, mw;
     u32 horizon_step, lookahead, flush_horizons, queue_cap;
     u32 threads, n_workers;
+    u32 horizon_mode, horizon_max_tasks;
     u32 cap_cmds, cap_allocs, cap_queue, cap_heap, cap_rb, cap_unit, cap_scr, cap_src, cap_box;
     u32 pad0;
     u64 cap_instr, cap_edges, cap_binds;

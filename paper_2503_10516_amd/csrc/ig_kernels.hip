@@ -1091,6 +1091,8 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
             sh.scan_tmp[3] = B.mask_off;
             sh.scan_tmp[4] = B.init_off;
             sh.scan_tmp[5] = B.stamp_off;
+            sh.scan_tmp[10] = B.wcp_off;
+            sh.scan_tmp[11] = B.rcp_off;
             sh.scan_tmp[6] = B.n[0];
             sh.scan_tmp[7] = B.n[1];
             sh.scan_tmp[8] = B.n[2];
@@ -1107,6 +1109,8 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
             B.mask_off = heap_alloc(c, sh, 2 * nc * c.mw);
             B.init_off = heap_alloc(c, sh, nc);
             B.stamp_off = heap_alloc(c, sh, 2 * nc);
+            B.wcp_off = heap_alloc(c, sh, nc);
+            B.rcp_off = heap_alloc(c, sh, nc);
             // allocations of this buffer: new cell boxes and arrays
             u32 na = 0;
             for (u32 m = 0; m < c.n_mem; ++m) {
@@ -1147,6 +1151,8 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
         W32(c, B.init_off)[cell] = iv;
         if (!iv) atomicAdd(&B.uninit, 1u);
         W64(c, B.stamp_off)[cell] = W64(c, sh.scan_tmp[5])[oc];
+        W32(c, B.wcp_off)[cell] = W32(c, sh.scan_tmp[10])[oc];
+        W32(c, B.rcp_off)[cell] = W32(c, sh.scan_tmp[11])[oc];
     }
     // --- allocation maps: every thread takes cells of every allocation
     // (each new cell comes from one old cell; reader blocks come from the
@@ -1176,6 +1182,8 @@ IGN void refine_buffer(DevCtx& c, Shared& sh, u32 b, const u64* keys, u32 lo, u3
     bar();
     if (tid() == 0) {
         for (u32 s = 1; s <= 5; ++s) heap_release(c, sh.scan_tmp[s]);
+        heap_release(c, sh.scan_tmp[10]);
+        heap_release(c, sh.scan_tmp[11]);
         for (u32 s = 0; s < na; ++s) heap_release(c, c.reg[s].buffer);
     }
     bar();
@@ -2928,6 +2936,72 @@ IGN void push_command(DevCtx& c, Shared& sh, u32 entry, bool allocating) {
 }
 
 // ===========================================================================
+// The task graph behind horizon mode 1 (Sec. 3.5): the critical-path length
+// of an accepted task is one more than the longest of the sync point and
+// the tasks it depends on.  Per buffer cell over the whole task's regions
+// (every chunk; reads see the state before the task): a read depends on the
+// last writer, a write on the readers since the last write, else on the
+// last writer.  Lengths below the sync point's read as it (horizon and
+// epoch compaction); a reader length at or below the latest epoch's is no
+// reader.  Then reads raise the cells' reader length and writes set the
+// writer length and clear the readers (a cell both read and written ends
+// written).
+// ===========================================================================
+IGN void task_graph_step(DevCtx& c, Shared& sh) {
+    const u32 A = sh.t_nacc, C = c.chunks;
+    if (tid() == 0) sh.flag = sh.s.cp_sync;
+    bar();
+    const u32 cp_epoch = sh.s.cp_epoch;
+    for (u32 idx = tid(); idx < C * A; idx += nt()) {
+        const u32 k = idx / A, j = idx % A;
+        const Region& r = c.reg[k * IG_MAX_ACCESS + j];
+        if (r.empty) continue;
+        const DBuf& B = c.bufs[r.buffer];
+        const u32* wcp = W32(c, B.wcp_off);
+        const u32* rcp = W32(c, B.rcp_off);
+        u32 d = 0;
+        for (u32 i0 = r.clo[0]; i0 < r.chi[0]; ++i0)
+            for (u32 i1 = r.clo[1]; i1 < r.chi[1]; ++i1)
+                for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2) {
+                    const u32 cell = cell_of(B, i0, i1, i2);
+                    const u32 w = wcp[cell], rd = rcp[cell];
+                    if (r.mode & IG_READ) d = d > w ? d : w;
+                    if (r.mode & IG_WRITE) {
+                        const u32 x = rd > cp_epoch ? rd : w;
+                        d = d > x ? d : x;
+                    }
+                }
+        atomicMax(&sh.flag, d);
+    }
+    bar();
+    const u32 cp = sh.flag + 1;
+    for (u32 pass = 0; pass < 2; ++pass) {
+        for (u32 idx = tid(); idx < C * A; idx += nt()) {
+            const u32 k = idx / A, j = idx % A;
+            const Region& r = c.reg[k * IG_MAX_ACCESS + j];
+            if (r.empty || !(r.mode & (pass == 0 ? IG_READ : IG_WRITE))) continue;
+            const DBuf& B = c.bufs[r.buffer];
+            u32* wcp = W32(c, B.wcp_off);
+            u32* rcp = W32(c, B.rcp_off);
+            for (u32 i0 = r.clo[0]; i0 < r.chi[0]; ++i0)
+                for (u32 i1 = r.clo[1]; i1 < r.chi[1]; ++i1)
+                    for (u32 i2 = r.clo[2]; i2 < r.chi[2]; ++i2) {
+                        const u32 cell = cell_of(B, i0, i1, i2);
+                        if (pass == 0) {
+                            atomicMax(&rcp[cell], cp);  // cp exceeds every length at or below the epoch's
+                        } else {
+                            wcp[cell] = cp;
+                            rcp[cell] = 0;
+                        }
+                    }
+        }
+        bar();
+    }
+    if (tid() == 0) sh.s.cp_max = sh.s.cp_max > cp ? sh.s.cp_max : cp;
+    bar();
+}
+
+// ===========================================================================
 // Command intake
 // ===========================================================================
 IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
@@ -3012,6 +3086,7 @@ IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
                     if (atomicExch(&init[cell_of(B, i0, i1, i2)], 1u) == 0) atomicAdd(&B.uninit, 0xFFFFFFFFu);
     }
     bar();
+    if (c.horizon_mode == 1) task_graph_step(c, sh);
     tick(c, sh, PH_INTAKE_CHECKS);
     const bool allocating = task_allocating(c, sh);
     if (tid() == 0) sh.t_covered = (sh.s.qlen == 0 && !allocating) ? 1u : 0u;
@@ -3023,7 +3098,17 @@ IGN void intake_task(DevCtx& c, Shared& sh, u32 ci) {
     if (tid() == 0) {
         sh.s.tasks_since_sync += 1;
         sh.do_horizon = 0;
-        if (sh.s.tasks_since_sync == c.horizon_step) {
+        if (c.horizon_mode == 1) {
+            // Sec. 3.5 from the task graph: the path grew by horizon_step
+            // since the last horizon or epoch, or enough tasks came since
+            if (sh.s.cp_max - sh.s.cp_last >= c.horizon_step || sh.s.tasks_since_sync >= c.horizon_max_tasks) {
+                if (sh.s.cp_pending) sh.s.cp_sync = sh.s.cp_pending;
+                sh.s.cp_pending = sh.s.cp_max + 1;
+                sh.s.cp_last = sh.s.cp_max;
+                sh.s.tasks_since_sync = 0;
+                sh.do_horizon = 1;
+            }
+        } else if (sh.s.tasks_since_sync == c.horizon_step) {
             sh.s.tasks_since_sync = 0;
             sh.do_horizon = 1;
         }
@@ -3061,7 +3146,11 @@ IGN void create_buffer(DevCtx& c, Shared& sh, const DevCmd& cmd) {
             B.mask_off = heap_alloc(c, sh, 2 * c.mw);
             B.init_off = heap_alloc(c, sh, 1);
             B.stamp_off = heap_alloc(c, sh, 2);
+            B.wcp_off = heap_alloc(c, sh, 1);
+            B.rcp_off = heap_alloc(c, sh, 1);
             if (!sh.s.error) {
+                W32(c, B.wcp_off)[0] = 0;
+                W32(c, B.rcp_off)[0] = 0;
                 W32(c, B.prod_off)[0] = cmd.init ? sh.s.S : NONE;
                 W32(c, B.pm_off)[0] = cmd.init ? 0 : NONE;
                 for (u32 w = 0; w < c.mw; ++w) W64(c, B.mask_off)[w] = (cmd.init && w == 0) ? 1ull : 0ull;
@@ -3358,6 +3447,8 @@ IGN void destroy_buffer(DevCtx& c, Shared& sh, u32 b) {
         heap_release(c, B.mask_off);
         heap_release(c, B.init_off);
         heap_release(c, B.stamp_off);
+        heap_release(c, B.wcp_off);
+        heap_release(c, B.rcp_off);
     }
     bar();
 }
@@ -3405,6 +3496,13 @@ IGD u32 done_prefix(const DevCtx& c, const Scalars& s) {
 
 // Analyse the uploaded commands from the context's position on; window > 0
 // stops after that many commands (the rest follows in later launches).
+// An epoch follows everything in the task graph so far (thread 0).
+IGD void epoch_task_graph(Shared& sh) {
+    const u32 e = sh.s.cp_max + 1;
+    sh.s.cp_epoch = sh.s.cp_sync = sh.s.cp_max = sh.s.cp_last = e;
+    sh.s.cp_pending = 0;
+}
+
 IGN void analyse(DevCtx& c, Shared& sh, u32 window) {
     if (tid() == 0) {
         sh.s = c.s;
@@ -3429,7 +3527,10 @@ IGN void analyse(DevCtx& c, Shared& sh, u32 window) {
                 break;
             case CMD_EPOCH:
                 flush_queue(c, sh);
-                if (tid() == 0) sh.s.tasks_since_sync = 0;
+                if (tid() == 0) {
+                    sh.s.tasks_since_sync = 0;
+                    epoch_task_graph(sh);
+                }
                 bar();
                 compile_sync(c, sh, true);
                 break;
@@ -3442,7 +3543,10 @@ IGN void analyse(DevCtx& c, Shared& sh, u32 window) {
                 const u32 nb = uniform(sh.s.n_buffers);
                 for (u32 b = 0; b < nb && !failed(sh); ++b)
                     if (uniform(c.bufs[b].alive)) destroy_buffer(c, sh, b);
-                if (tid() == 0) sh.s.tasks_since_sync = 0;
+                if (tid() == 0) {
+                    sh.s.tasks_since_sync = 0;
+                    epoch_task_graph(sh);
+                }
                 bar();
                 compile_sync(c, sh, true);
                 if (tid() == 0) sh.s.finished = 1;

@@ -708,6 +708,100 @@ def _merge_components(boxes):
     return v
 
 
+def tdag_horizons(stream, status) -> List[bool]:
+    """Horizon placement of the task-graph mode (Sec. 3.5), from an explicit
+    task graph built element by element: for each accepted task in order,
+    whether a horizon follows it.
+
+    Nodes are numbered in creation order (the initial epoch is 0; tasks,
+    horizons and epochs follow).  Per buffer element: the last writer node
+    and the reader nodes since.  A read depends on the writer; a write on
+    the readers, else the writer; a task without dependencies on the
+    synchronisation node.  The critical-path length of a node is one more
+    than its dependencies' longest.  A horizon follows a task once the
+    longest path has grown by horizon_step since the last horizon or epoch,
+    or horizon_max_tasks tasks came since; it depends on everything, so its
+    length is the longest plus one, and it makes the horizon before it the
+    synchronisation node: every older writer or reader is replaced by that
+    one.  An epoch replaces every writer and clears the readers."""
+    step = stream.horizon_step
+    cap = stream.horizon_max_tasks or 16 * step
+    cp = [0]
+    sync, pending = 0, None
+    cp_max = cp_last = since = 0
+    bufs = []
+    out = []
+    ti = 0
+
+    def apply(node):
+        for b in bufs:
+            for p in b["w"]:
+                if b["w"][p] < node:
+                    b["w"][p] = node
+                b["r"][p] = {node if r < node else r for r in b["r"][p]}
+
+    for c in stream.cmds:
+        if c[0] == "buffer":
+            pts = box_points(((0, 0, 0), c[2]))
+            bufs.append({"dims": c[1], "ext": c[2], "w": {p: 0 for p in pts}, "r": {p: set() for p in pts}})
+        elif c[0] == "task":
+            t = c[1]
+            ok = int(status[ti]) >= 0
+            ti += 1
+            if not ok:
+                continue
+            regions = []
+            for ch in split_py(stream.nodes, stream.devices, stream.chunks, t.lo, t.hi):
+                if box_empty(ch):
+                    continue
+                for a in t.accesses:
+                    b = bufs[a.buffer]
+                    regions.append((a, box_points(map_py(a, ch, b["dims"], b["ext"]))))
+            deps = {sync}
+            for a, pts in regions:
+                b = bufs[a.buffer]
+                for p in pts:
+                    if a.mode & READ:
+                        deps.add(b["w"][p])
+                    if a.mode & WRITE:
+                        deps |= b["r"][p] if b["r"][p] else {b["w"][p]}
+            node = len(cp)
+            cp.append(1 + max(cp[d] for d in deps))
+            for want in (READ, WRITE):
+                for a, pts in regions:
+                    if not (a.mode & want):
+                        continue
+                    b = bufs[a.buffer]
+                    for p in pts:
+                        if want == READ:
+                            b["r"][p].add(node)
+                        else:
+                            b["w"][p] = node
+                            b["r"][p] = set()
+            cp_max = max(cp_max, cp[node])
+            since += 1
+            due = cp_max - cp_last >= step or since >= cap
+            out.append(due)
+            if due:
+                h = len(cp)
+                cp.append(cp_max + 1)
+                if pending is not None:
+                    apply(pending)
+                    sync = pending
+                pending, cp_last, since = h, cp_max, 0
+        elif c[0] in ("epoch", "shutdown"):
+            e = len(cp)
+            cp.append(cp_max + 1)
+            for b in bufs:
+                for p in b["w"]:
+                    b["w"][p] = e
+                    b["r"][p] = set()
+            sync, pending = e, None
+            cp_max = cp_last = cp[e]
+            since = 0
+    return out
+
+
 def check_queue(stream, out, tasks) -> int:
     """The lookahead queue (Sec. 4.3) replayed from the command trace.
 
@@ -740,6 +834,7 @@ def check_queue(stream, out, tasks) -> int:
         elif c[0] == "shutdown":
             seq.append(EV_SHUTDOWN)
     kinds = [int(e["kind"]) for e in ev]
+    tdag = iter(tdag_horizons(stream, out["status"])) if getattr(stream, "horizon_mode", 0) == 1 else None
     i = 0
     for want in seq:
         _require(i < len(kinds), "command trace ends early")
@@ -747,10 +842,13 @@ def check_queue(stream, out, tasks) -> int:
             _require(kinds[i] in (EV_TASK, EV_REJECTED), f"event {i}: expected a task, got {kinds[i]}")
             if kinds[i] == EV_TASK:
                 since += 1
-                if since == stream.horizon_step:
+                due = next(tdag) if tdag is not None else since == stream.horizon_step
+                if due:
                     since = 0
                     i += 1
-                    _require(kinds[i] == EV_HORIZON, f"event {i}: a horizon after {stream.horizon_step} tasks")
+                    _require(i < len(kinds) and kinds[i] == EV_HORIZON, f"event {i}: a horizon is due")
+                else:
+                    _require(i + 1 >= len(kinds) or kinds[i + 1] != EV_HORIZON, f"event {i + 1}: no horizon is due")
         else:
             _require(kinds[i] == want, f"event {i}: expected {want}, got {kinds[i]}")
             if want in (EV_EPOCH, EV_SHUTDOWN):

@@ -270,6 +270,15 @@ def test_sim_big_reads(variant, threads, sim_lib):
     assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=threads), s.name)
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_sim_task_graph_horizons(seed, sim_lib):
+    """Horizons from the task graph (horizon mode 1, Sec. 3.5) in the kernel
+    equal the oracle's, record by record."""
+    from test_oracle_semantics import tdag_stream
+    s = tdag_stream(seed)
+    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64), s.name)
+
+
 @pytest.mark.parametrize("index", [0, 3, 7])
 def test_sim_batched_generator_streams(index, sim_lib):
     s = S.batched_stream(S.BATCHED_SEED, index, max_tasks=60, max_log_chunks=6, max_log_extent=12)

@@ -281,6 +281,34 @@ def test_big_reads_team_scans(variant, threads):
     assert_same(want, got, f"{s.name}_t{threads}")
 
 
+@pytest.mark.parametrize("seed", range(24))
+def test_task_graph_horizons(seed):
+    """Horizons from the task graph (horizon mode 1, Sec. 3.5): random
+    streams, with low caps on the tasks between horizons for some."""
+    from test_oracle_semantics import tdag_stream
+    s = tdag_stream(seed)
+    want, got = run_both(s)
+    assert_same(want, got, s.name)
+
+
+TDAG_LARGE = [
+    ("stencil2d", lambda: S.stencil_2d(side=512, tasks=40, nodes=2, devices=4, chunks=16)),
+    ("nbody", lambda: S.nbody(n=4096, steps=8, nodes=4, devices=4, chunks=32)),
+    ("growing_q4", lambda: S.growing(width=840, steps=32, queue_cap=4)),
+    ("batched_0", lambda: S.batched_stream(S.BATCHED_SEED, 0, max_tasks=300, w_all=0.05, w_slice=0.05)),
+    ("batched_5", lambda: S.batched_stream(S.BATCHED_SEED, 5, max_tasks=300, w_all=0.05, w_slice=0.05)),
+]
+
+
+@pytest.mark.parametrize("name,make", TDAG_LARGE, ids=[t[0] for t in TDAG_LARGE])
+def test_task_graph_horizons_larger_streams(name, make):
+    s = make()
+    s.horizon_mode = 1
+    s.name += "_tdag"
+    want, got = run_both(s)
+    assert_same(want, got, s.name)
+
+
 @pytest.mark.parametrize("seed", range(40))
 def test_racy_random_streams(seed):
     """Reads of regions that other chunks of the same task write (a user

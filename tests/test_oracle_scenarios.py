@@ -165,3 +165,58 @@ def check_group_order(out):
 
 def test_copy_group_order_hand_worked():
     check_group_order(oracle.run_stream(group_order_stream()))
+
+
+# ---------------------------------------------------------------------------
+# Horizons from the task graph (Sec. 3.5, horizon_mode 1)
+# ---------------------------------------------------------------------------
+CHAINS = [
+    ("stencil1d", lambda: S.stencil_1d()),
+    ("stencil2d", lambda: S.stencil_2d(side=256, tasks=40, nodes=2, devices=4, chunks=16)),
+    ("nbody", lambda: S.nbody(n=4096, steps=10, nodes=2, devices=4, chunks=16)),
+    ("growing", lambda: S.growing(width=840, steps=40)),
+    ("growing_nola", lambda: S.growing(width=840, steps=24, lookahead=0)),
+    ("nbody_example", S.nbody_example),
+]
+
+
+@pytest.mark.parametrize("name,make", CHAINS, ids=[c[0] for c in CHAINS])
+def test_tdag_horizons_equal_fixed_step_on_chains(name, make):
+    """In these workloads every task depends on the one before it, so the
+    critical path grows by one per task and the task graph asks for a
+    horizon exactly every horizon_step tasks: the same graph, record by
+    record, as the fixed step (282 instructions for the 1-D stencil)."""
+    a, b = make(), make()
+    b.horizon_mode = 1
+    ra, rb = oracle.run_stream(a), oracle.run_stream(b)
+    for k in ("instructions", "bindings", "edges"):
+        assert ra[k].tobytes() == rb[k].tobytes(), (name, k)
+    if name == "stencil1d":
+        assert len(rb["instructions"]) == 282
+
+
+def test_tdag_independent_tasks_horizon_by_width():
+    """Tasks on four disjoint buffers, task t on buffer t mod 4: task t
+    depends only on task t - 4, so the critical path grows by one every four
+    tasks.  Worked by hand: with a step of 4 the path alone asks for a
+    horizon after task 13 (path length 4) and task 29 (length 8, four more
+    than at the first horizon); a cap of 6 tasks between horizons comes
+    first, after tasks 6, 12, 18, 24 and 30."""
+    def make(cap):
+        s = S.Stream(1, 2, 2, lookahead=0, horizon_mode=1, horizon_max_tasks=cap)
+        bufs = [s.buffer(1, (16,), 4, S.INIT_HOST) for _ in range(4)]
+        for t in range(32):
+            s.task(1, (0,), (16,), [S.Access(bufs[t % 4], S.READ_WRITE, S.ONE_TO_ONE)])
+        s.shutdown()
+        return s
+    for cap, want in ((100, [13, 29]), (6, [6, 12, 18, 24, 30])):
+        ev = oracle.run_stream(make(cap))["events"]
+        kinds = [int(e["kind"]) for e in ev]
+        tasks_before = []
+        n = 0
+        for k in kinds:
+            if k == oracle.EV_TASK:
+                n += 1
+            elif k == oracle.EV_HORIZON:
+                tasks_before.append(n)
+        assert tasks_before == want, (cap, tasks_before)

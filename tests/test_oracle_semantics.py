@@ -45,6 +45,25 @@ def test_random_streams_bruteforce(seed):
     check_stream(s, oracle.run_stream(s), seed=seed)
 
 
+def tdag_stream(seed):
+    """A random stream with horizons from the task graph (Sec. 3.5); every
+    third one caps the tasks between horizons low."""
+    s = S.random_small(seed, n_tasks=16)
+    s.horizon_mode = 1
+    s.horizon_max_tasks = 3 if seed % 3 == 0 else 0
+    s.horizon_step = 2 + seed % 3
+    s.name += "_tdag"
+    return s
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_streams_tdag_horizons_bruteforce(seed):
+    """Horizon placement from an explicit element-level task graph, plus
+    every other brute-force check, with horizons from the task graph."""
+    s = tdag_stream(seed)
+    check_stream(s, oracle.run_stream(s), seed=seed)
+
+
 def test_overlapping_write_rejected_atomically():
     s = S.Stream(1, 2, 2, lookahead=0)
     b = s.buffer(1, (8,), 4, S.INIT_HOST)
@@ -97,6 +116,13 @@ MUTANTS = {
     "horizon_misses_front": ("for (uint32_t f : front) s.add(f, IGO_DEP_SYNC);\n        finish(hi, s);",
                               "if (!front.empty()) s.add(*front.begin(), IGO_DEP_SYNC);\n        finish(hi, s);"),
     "no_sync_fallback": ("if (s.from.empty()) s.add(sync_point, IGO_DEP_SYNC);", ";"),
+    # task-graph horizons (horizon_mode 1)
+    "tdag_write_ignores_readers": ("if (rg.mode & IGO_WRITE) d = std::max(d, e.rcp > cp_epoch ? eff(e.rcp) : eff(e.wcp));",
+                                   "if (rg.mode & IGO_WRITE) d = std::max(d, eff(e.wcp));"),
+    "tdag_reads_not_recorded": ("in.rcp = std::max(in.rcp > cp_epoch ? in.rcp : 0u, cp);", ";"),
+    "tdag_horizon_late": ("c->cp_last = c->cp_max;", "c->cp_last = c->cp_max + 1;"),
+    "tdag_pending_not_applied": ("if (c->cp_pending) c->cp_sync = c->cp_pending;", ";"),
+    "tdag_cap_off_by_one": ("++c->tasks_since_sync >= c->horizon_max_tasks", "++c->tasks_since_sync > c->horizon_max_tasks"),
     "no_overlap_check": ("if (v[i].second != v[j].second && intersects(v[i].first, v[j].first)) {",
                          "if (false) {"),
     "producer_split_off": ("groups[std::make_tuple(e.pm, e.producer, a)]", "groups[std::make_tuple(e.pm, 0u, a)]"),
@@ -144,7 +170,8 @@ def _overlap_stream():
     return s
 
 
-MUTANT_STREAMS = [_overlap_stream()] + [S.random_small(seed) for seed in range(40)] + [
+MUTANT_STREAMS = [_overlap_stream()] + [S.random_small(seed) for seed in range(40)] + \
+    [tdag_stream(seed) for seed in range(24)] + [
     S.nbody(n=24, steps=4, nodes=2, devices=2, chunks=8),
     S.stencil_2d(side=12, tasks=9, nodes=2, devices=2, chunks=4),
     S.growing(width=12, steps=8, devices=4, lookahead=0),
