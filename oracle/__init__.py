@@ -333,3 +333,47 @@ def digest_words(words: np.ndarray) -> int:
     w = np.ascontiguousarray(words, dtype=np.uint64)
     n, k = (w.shape[0], w.shape[1]) if w.ndim == 2 else (0, 1)
     return int(lib().igo_digest(w.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n, k))
+
+
+# --- the out-of-order engine of Sec. 4.1, simulated over a finished graph ---
+
+class OooParams(ctypes.Structure):
+    _fields_ = [("devices", ctypes.c_uint32), ("lanes_per_device", ctypes.c_uint32),
+                ("host_lanes", ctypes.c_uint32), ("window", ctypes.c_uint32), ("eager", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("kernel_ns", ctypes.c_uint64), ("kernel_ns_per_kelem", ctypes.c_uint64),
+                ("copy_ns", ctypes.c_uint64), ("copy_ns_per_kelem", ctypes.c_uint64),
+                ("inter_node_ns", ctypes.c_uint64), ("alloc_ns", ctypes.c_uint64), ("free_ns", ctypes.c_uint64)]
+
+
+class OooSummary(ctypes.Structure):
+    _fields_ = [("makespan", ctypes.c_uint64), ("direct", ctypes.c_uint64), ("eager", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("rounds", ctypes.c_uint64)]
+
+
+OOO_SLOT_DTYPE = np.dtype([("lane", "<u4"), ("how", "<u4"), ("issue", "<u8"), ("start", "<u8"), ("end", "<u8")])
+OOO_ENGINE, OOO_DIRECT, OOO_EAGER = 0, 1, 2
+
+
+def ooo_params(devices, lanes_per_device=2, host_lanes=2, window=1024, eager=1, kernel_ns=4000,
+               kernel_ns_per_kelem=64, copy_ns=2000, copy_ns_per_kelem=32, inter_node_ns=8000, alloc_ns=20000,
+               free_ns=5000) -> OooParams:
+    return OooParams(devices, lanes_per_device, host_lanes, window, eager, 0, kernel_ns, kernel_ns_per_kelem,
+                     copy_ns, copy_ns_per_kelem, inter_node_ns, alloc_ns, free_ns)
+
+
+def ooo_simulate(instructions: np.ndarray, edges: np.ndarray, params: OooParams):
+    """(slots, summary) of the engine over records in the layouts above."""
+    L = lib()
+    fn = L.igo_ooo_simulate
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(OooParams),
+                   ctypes.c_void_p, ctypes.POINTER(OooSummary)]
+    fn.restype = ctypes.c_int32
+    ins = np.ascontiguousarray(instructions, dtype=INSTR_DTYPE)
+    ed = np.ascontiguousarray(edges, dtype=EDGE_DTYPE)
+    out = np.zeros(len(ins), dtype=OOO_SLOT_DTYPE)
+    summ = OooSummary()
+    st = fn(ins.ctypes.data, len(ins), ed.ctypes.data, len(ed), ctypes.byref(params), out.ctypes.data,
+            ctypes.byref(summ))
+    if st != 0:
+        raise ValueError(f"igo_ooo_simulate failed: {st}")
+    return out, {k: getattr(summ, k) for k, _ in OooSummary._fields_}

@@ -16,6 +16,8 @@
  *                                     legend of the IDAG figure (Sec. 3.6)
  *   topological emission order ...... Sec. 4.1
  *   lookahead / command queue ....... Sec. 4.3
+ *   out-of-order engine (simulated) . Sec. 4.1 (direct and eager assignment
+ *                                     to in-order lanes)
  *   uninitialised-read and
  *   overlapping-write detection ..... Sec. 4.4
  * The readings that settle what the paper leaves open are listed in the
@@ -1435,6 +1437,123 @@ int32_t igo_map(const igo_access* acc, uint32_t task_dims, const igo_box* chunk,
     for (int d = 0; d < 3; ++d) ext[d] = (uint32_t)d < buf_dims ? extent[d] : 1;
     Box r = map_range(*acc, from_igo(*chunk), buf_dims, ext);
     *out = to_igo(r);
+    return IGO_OK;
+}
+
+// Sec. 4.1: the out-of-order engine, simulated (see igo_ooo_simulate in the
+// header for the rules).
+int32_t igo_ooo_simulate(const igo_instruction* ins, size_t n, const igo_edge* edges, size_t n_edges,
+                         const igo_ooo_params* p, igo_ooo_slot* out, igo_ooo_summary* sum) {
+    if ((!ins && n) || (!edges && n_edges) || !p || (!out && n) || !sum) return IGO_E_INVALID;
+    if (p->lanes_per_device == 0 || p->host_lanes == 0 || p->window == 0 || p->eager > 1) return IGO_E_INVALID;
+    const uint64_t INF = ~0ull;
+    const uint32_t Q = p->lanes_per_device, host0 = p->devices * Q, n_lanes = host0 + p->host_lanes;
+    std::vector<std::vector<uint32_t>> deps(n);
+    for (size_t e = 0; e < n_edges; ++e) {
+        if (edges[e].to >= n || edges[e].from >= edges[e].to) return IGO_E_INVALID;
+        deps[edges[e].to].push_back((uint32_t)edges[e].from);
+    }
+    // the lanes an instruction may go to: [lo, hi); lo == hi: the engine's own
+    std::vector<uint32_t> lo(n), hi(n);
+    std::vector<uint64_t> dur(n);
+    for (size_t x = 0; x < n; ++x) {
+        const igo_instruction& r = ins[x];
+        if (r.id != x) return IGO_E_INVALID;
+        uint64_t vol = 1;
+        for (int d = 0; d < 3; ++d) vol *= (uint64_t)(r.box.max[d] > r.box.min[d] ? r.box.max[d] - r.box.min[d] : 0);
+        uint32_t dev = NONE;
+        if (r.kind == IGO_KERNEL) {
+            dev = r.mem;
+            dur[x] = p->kernel_ns + vol * p->kernel_ns_per_kelem / 1024;
+        } else if (r.kind == IGO_COPY) {
+            dev = r.mem >= 2 ? r.mem : NONE;
+            dur[x] = p->copy_ns + vol * p->copy_ns_per_kelem / 1024 + ((r.flags & IGO_F_INTER_NODE) ? p->inter_node_ns : 0);
+        } else if (r.kind == IGO_ALLOC) {
+            dur[x] = p->alloc_ns;
+        } else if (r.kind == IGO_FREE) {
+            dur[x] = p->free_ns;
+        } else {
+            lo[x] = hi[x] = 0;  // horizon, epoch
+            dur[x] = 0;
+            continue;
+        }
+        if (dev != NONE) {
+            if (dev < 2 || dev - 2 >= p->devices) return IGO_E_INVALID;
+            lo[x] = (dev - 2) * Q;
+            hi[x] = lo[x] + Q;
+        } else {
+            lo[x] = host0;
+            hi[x] = n_lanes;
+        }
+    }
+    std::vector<bool> assigned(n, false);
+    std::vector<uint64_t> end(n, INF);
+    std::vector<uint64_t> busy(n_lanes, 0);
+    std::memset(sum, 0, sizeof *sum);
+    uint64_t t = 0;
+    size_t first = 0;
+    while (first < n) {
+        ++sum->steps;
+        while (true) {
+            // which instructions are assignable at the start of this round
+            const size_t last = std::min(n, first + (size_t)p->window);
+            std::vector<std::pair<size_t, uint32_t>> take;  // (instruction, eager lane or NONE for direct)
+            for (size_t x = first; x < last; ++x) {
+                if (assigned[x]) continue;
+                std::vector<uint32_t> open;
+                for (uint32_t d : deps[x])
+                    if (!(assigned[d] && end[d] <= t)) open.push_back(d);
+                if (open.empty()) {
+                    take.push_back({x, NONE});
+                    continue;
+                }
+                if (!p->eager || lo[x] == hi[x]) continue;
+                bool same = true;
+                const uint32_t L = assigned[open[0]] ? out[open[0]].lane : NONE;
+                for (uint32_t d : open) same = same && assigned[d] && out[d].lane == L;
+                if (same && L != NONE && L >= lo[x] && L < hi[x]) take.push_back({x, L});
+            }
+            if (take.empty()) break;
+            ++sum->rounds;
+            for (const auto& tk : take) {
+                const size_t x = tk.first;
+                igo_ooo_slot& o = out[x];
+                o.issue = t;
+                if (lo[x] == hi[x]) {
+                    o.lane = NONE;
+                    o.how = IGO_OOO_ENGINE;
+                    o.start = o.end = t;
+                } else {
+                    uint32_t L = tk.second;
+                    if (L == NONE) {
+                        L = lo[x];
+                        for (uint32_t q = lo[x] + 1; q < hi[x]; ++q)
+                            if (busy[q] < busy[L]) L = q;
+                        o.how = IGO_OOO_DIRECT;
+                        ++sum->direct;
+                    } else {
+                        o.how = IGO_OOO_EAGER;
+                        ++sum->eager;
+                    }
+                    o.lane = L;
+                    o.start = std::max(t, busy[L]);
+                    o.end = o.start + dur[x];
+                    busy[L] = o.end;
+                }
+                assigned[x] = true;
+                end[x] = o.end;
+                sum->makespan = std::max(sum->makespan, o.end);
+            }
+            while (first < n && assigned[first]) ++first;
+        }
+        if (first >= n) break;
+        // the next completion
+        uint64_t nt = INF;
+        for (size_t x = 0; x < n; ++x)
+            if (assigned[x] && end[x] > t) nt = std::min(nt, end[x]);
+        if (nt == INF) return IGO_E_INVALID;  // nothing in flight and nothing assignable: not a DAG
+        t = nt;
+    }
     return IGO_OK;
 }
 

@@ -221,6 +221,62 @@ int32_t igo_map(const igo_access* acc, uint32_t task_dims, const igo_box* chunk,
                 uint32_t buf_dims, const int64_t extent[3], igo_box* out);
 uint64_t igo_digest(const uint64_t* words, size_t n_records, size_t words_per_record);
 
+/* ---------------------------------------------------------------------------
+ * Out-of-order engine (Sec. 4.1), simulated over a finished instruction
+ * graph.  Lanes are in-order queues: lanes_per_device per device (device
+ * memory 2 + d) for its kernels and the copies into it, and host_lanes for
+ * allocations, frees and copies into host memory; horizons and epochs
+ * complete in the engine itself when their dependencies have.  Time is
+ * integer nanoseconds.  At each moment the engine makes rounds over the
+ * unassigned instructions whose ids lie within `window` of the first
+ * unassigned one: a round takes every one that is assignable at its start,
+ * in id order -- directly when all its dependencies are complete (to the
+ * lane of its class that frees up first, lowest number on ties), or, with
+ * `eager`, eagerly when every incomplete dependency is issued to one and
+ * the same lane of its class (behind them, which the lane's order makes
+ * safe).  When a round takes none, time moves to the next completion.
+ * --------------------------------------------------------------------------- */
+typedef struct igo_ooo_params {
+    uint32_t devices;            /* device memories 2 .. devices + 1 */
+    uint32_t lanes_per_device;   /* >= 1 */
+    uint32_t host_lanes;         /* >= 1 */
+    uint32_t window;             /* >= 1 */
+    uint32_t eager;              /* 0 or 1 */
+    uint32_t pad;
+    uint64_t kernel_ns;          /* KERNEL: kernel_ns + volume * kernel_ns_per_kelem / 1024 */
+    uint64_t kernel_ns_per_kelem;
+    uint64_t copy_ns;            /* COPY: copy_ns + volume * copy_ns_per_kelem / 1024 (+ inter_node_ns) */
+    uint64_t copy_ns_per_kelem;
+    uint64_t inter_node_ns;
+    uint64_t alloc_ns;
+    uint64_t free_ns;
+} igo_ooo_params;
+
+#define IGO_OOO_ENGINE 0u  /* horizon / epoch: completed by the engine */
+#define IGO_OOO_DIRECT 1u
+#define IGO_OOO_EAGER 2u
+
+typedef struct igo_ooo_slot {
+    uint32_t lane;   /* IGO_NONE32 for the engine's own instructions */
+    uint32_t how;    /* IGO_OOO_* */
+    uint64_t issue;  /* the moment it was assigned */
+    uint64_t start;
+    uint64_t end;
+} igo_ooo_slot; /* 32 bytes */
+
+typedef struct igo_ooo_summary {
+    uint64_t makespan;
+    uint64_t direct, eager;
+    uint64_t steps;   /* moments at which rounds ran */
+    uint64_t rounds;
+} igo_ooo_summary;
+
+/* ins[i].id must be i; edges in any order with from < to.  Returns
+ * IGO_E_INVALID on bad arguments or an instruction whose memory has no
+ * lane. */
+int32_t igo_ooo_simulate(const igo_instruction* ins, size_t n, const igo_edge* edges, size_t n_edges,
+                         const igo_ooo_params* p, igo_ooo_slot* out, igo_ooo_summary* sum);
+
 #ifdef __cplusplus
 }
 #endif
