@@ -457,6 +457,83 @@ ig_status ig_fetch_task_times(ig_context* ctx, double* dst, size_t cap, size_t* 
  * digests, all computed on the device. */
 ig_status ig_stats_get(ig_context* ctx, ig_stats* out);
 
+/* ---------------------------------------------------------------------------
+ * Out-of-order engine (Sec. 4.1), simulated on the device over finished
+ * graphs.  The executor keeps several in-order queues ("lanes") per device
+ * for its kernels and the copies into it, and host lanes for allocations,
+ * frees and copies into host memory; horizons and epochs complete in the
+ * engine itself once their dependencies have.  An instruction is assigned
+ * directly when every dependency is complete (to the lane of its class that
+ * frees up first, the lowest on ties), or, with `eager`, eagerly when every
+ * incomplete dependency sits on one and the same lane of its class, behind
+ * which the lane's FIFO order makes it safe.  Time is integer nanoseconds
+ * under the cost model below.  At each moment the engine makes rounds over
+ * the unassigned instructions whose ids lie within `window` of the first
+ * unassigned one; a round takes every one that is assignable at its start,
+ * in id order; when a round takes none, time moves to the next completion.
+ *
+ * One workgroup simulates one graph; a handle simulates several graphs (one
+ * per context) in one launch.  The graphs are the contexts' records as they
+ * stand at ig_ooo_create (after ig_sync); records analysed afterwards are
+ * not seen until the handle is created again.
+ * --------------------------------------------------------------------------- */
+#define IG_OOO_MAX_WINDOW 4096u
+#define IG_OOO_MAX_LANES 1024u  /* devices * lanes_per_device + host_lanes */
+#define IG_OOO_ENGINE 0u        /* horizon / epoch: completed by the engine */
+#define IG_OOO_DIRECT 1u
+#define IG_OOO_EAGER 2u
+
+typedef struct ig_ooo_params {
+    uint32_t devices;            /* lanes for device memories 2 .. devices + 1 */
+    uint32_t lanes_per_device;   /* >= 1 */
+    uint32_t host_lanes;         /* >= 1 */
+    uint32_t window;             /* 1 .. IG_OOO_MAX_WINDOW */
+    uint32_t eager;              /* 0 or 1 */
+    uint32_t pad;
+    uint64_t kernel_ns;          /* KERNEL: kernel_ns + volume * kernel_ns_per_kelem / 1024, volume of its box */
+    uint64_t kernel_ns_per_kelem;
+    uint64_t copy_ns;            /* COPY: copy_ns + volume * copy_ns_per_kelem / 1024, + inter_node_ns */
+    uint64_t copy_ns_per_kelem;  /*       when IG_F_INTER_NODE */
+    uint64_t inter_node_ns;
+    uint64_t alloc_ns;           /* ALLOC */
+    uint64_t free_ns;            /* FREE; kernel_ns, copy_ns, alloc_ns and free_ns must be >= 1 */
+} ig_ooo_params;
+
+typedef struct ig_ooo_slot {
+    uint32_t lane;   /* lane d * lanes_per_device + q for device memory 2 + d; host lanes follow;
+                        IG_NONE32 for the engine's own instructions */
+    uint32_t how;    /* IG_OOO_* */
+    uint64_t issue;  /* the moment it was assigned */
+    uint64_t start;
+    uint64_t end;
+} ig_ooo_slot; /* 32 bytes, one per instruction, in id order */
+
+typedef struct ig_ooo_summary {
+    uint64_t makespan;       /* the last end */
+    uint64_t direct, eager;  /* assignments of each kind */
+    uint64_t steps;          /* moments at which rounds ran */
+    uint64_t rounds;         /* rounds that assigned something */
+} ig_ooo_summary;
+
+typedef struct ig_ooo ig_ooo;
+/* A simulation handle over the graphs of n contexts (synchronises each
+ * context's stream to read its record counts).  Allocates device memory for
+ * the per-instruction results and a workspace of 28 bytes per instruction
+ * and 4 per edge.  Errors: IG_E_INVALID (parameters out of range, a context
+ * with an analysis error, more than 2^31 - 1 instructions), IG_E_DEVICE. */
+ig_status ig_ooo_create(ig_context* const* ctxs, size_t n, const ig_ooo_params* p, ig_ooo** out);
+/* Queue the simulation of every graph on `stream` (asynchronous). */
+ig_status ig_ooo_run(ig_ooo* o, void* stream);
+/* Device address and length of graph i's results (owned by the handle,
+ * valid until ig_ooo_destroy, complete once the run's stream has reached
+ * them). */
+ig_status ig_ooo_slots(ig_ooo* o, size_t i, ig_ooo_slot** d_slots, uint64_t* n);
+/* Wait for the last run and copy graph i's results (up to cap) and summary
+ * (may be NULL) to the host.  Returns the graph's status: IG_E_INVALID for a
+ * record the engine has no lane for (a device memory beyond `devices`). */
+ig_status ig_ooo_fetch(ig_ooo* o, size_t i, ig_ooo_slot* dst, size_t cap, size_t* n_out, ig_ooo_summary* sum);
+ig_status ig_ooo_destroy(ig_ooo* o);
+
 const char* ig_status_str(ig_status st);
 
 /* The message of the last HIP runtime error this thread's calls saw (the

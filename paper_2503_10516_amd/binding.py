@@ -28,6 +28,9 @@ EDGE_DTYPE = np.dtype([("from", "<u8"), ("to", "<u8"), ("kinds", "<u4"), ("pad",
 IG_OK, IG_W_UNINIT_READ, IG_E_INVALID, IG_E_OVERLAPPING_WRITE, IG_E_CAPACITY, IG_E_DEVICE, IG_E_BUSY = \
     0, 1, -1, -2, -3, -4, -5
 IG_E_INTERNAL = -6
+IG_ALLOC, IG_COPY, IG_FREE, IG_KERNEL, IG_HORIZON, IG_EPOCH = 1, 2, 3, 4, 5, 6
+IG_F_RESIZE, IG_F_INTER_NODE = 1, 2
+IG_OOO_ENGINE, IG_OOO_DIRECT, IG_OOO_EAGER = 0, 1, 2
 
 
 class IgError(RuntimeError):
@@ -83,6 +86,22 @@ class Stats(ctypes.Structure):
                 ("phase_us", ctypes.c_double * 16), ("phase_count", ctypes.c_uint64 * 16)]
 
 
+class OooParams(ctypes.Structure):
+    _fields_ = [("devices", ctypes.c_uint32), ("lanes_per_device", ctypes.c_uint32),
+                ("host_lanes", ctypes.c_uint32), ("window", ctypes.c_uint32), ("eager", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("kernel_ns", ctypes.c_uint64), ("kernel_ns_per_kelem", ctypes.c_uint64),
+                ("copy_ns", ctypes.c_uint64), ("copy_ns_per_kelem", ctypes.c_uint64),
+                ("inter_node_ns", ctypes.c_uint64), ("alloc_ns", ctypes.c_uint64), ("free_ns", ctypes.c_uint64)]
+
+
+class OooSummary(ctypes.Structure):
+    _fields_ = [("makespan", ctypes.c_uint64), ("direct", ctypes.c_uint64), ("eager", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("rounds", ctypes.c_uint64)]
+
+
+OOO_SLOT_DTYPE = np.dtype([("lane", "<u4"), ("how", "<u4"), ("issue", "<u8"), ("start", "<u8"), ("end", "<u8")])
+
+
 EXPORTS = [
     "ig_arena_bytes", "ig_context_create", "ig_context_destroy", "ig_buffer_create",
     "ig_buffer_destroy", "ig_submit_task", "ig_submit_tasks", "ig_epoch", "ig_shutdown",
@@ -92,6 +111,7 @@ EXPORTS = [
     "ig_batch_graph_create", "ig_graph_launch", "ig_graph_destroy", "ig_batch_flush_window",
     "ig_batch_progress_noalloc", "ig_server_create", "ig_server_destroy", "ig_server_admit", "ig_server_session",
     "ig_server_submit", "ig_server_poll", "ig_server_detach", "ig_last_error",
+    "ig_ooo_create", "ig_ooo_run", "ig_ooo_slots", "ig_ooo_fetch", "ig_ooo_destroy",
 ]
 
 _libs: Dict[str, ctypes.CDLL] = {}
@@ -133,6 +153,11 @@ def lib(path: Optional[str] = None) -> ctypes.CDLL:
     L.ig_batch_graph_create.argtypes = [P(vp), ctypes.c_size_t, vp, P(vp)]
     L.ig_graph_launch.argtypes = [vp, vp]
     L.ig_graph_destroy.argtypes = [vp]
+    L.ig_ooo_create.argtypes = [P(vp), ctypes.c_size_t, P(OooParams), P(vp)]
+    L.ig_ooo_run.argtypes = [vp, vp]
+    L.ig_ooo_slots.argtypes = [vp, ctypes.c_size_t, P(vp), P(ctypes.c_uint64)]
+    L.ig_ooo_fetch.argtypes = [vp, ctypes.c_size_t, vp, ctypes.c_size_t, P(ctypes.c_size_t), P(OooSummary)]
+    L.ig_ooo_destroy.argtypes = [vp]
     L.ig_counts.argtypes = [vp] + [P(ctypes.c_uint64)] * 4
     for n in ("ig_fetch_instructions", "ig_fetch_bindings", "ig_fetch_edges", "ig_fetch_task_status"):
         getattr(L, n).argtypes = [vp, vp, ctypes.c_size_t, P(ctypes.c_size_t)]
@@ -657,6 +682,65 @@ class Server:
             self.L.ig_server_destroy(self.h)
             self.h = ctypes.c_void_p()
         self.sessions = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ooo_params(devices, lanes_per_device=2, host_lanes=2, window=1024, eager=1, kernel_ns=4000,
+               kernel_ns_per_kelem=64, copy_ns=2000, copy_ns_per_kelem=32, inter_node_ns=8000, alloc_ns=20000,
+               free_ns=5000) -> OooParams:
+    """Engine parameters (ig_ooo_params); the defaults are the cost model
+    the benchmark uses: 4 us per kernel plus 64 ns per 1024 index points,
+    2 us per copy plus 32 ns per 1024 elements (+8 us between nodes), 20 us
+    per allocation, 5 us per free."""
+    return OooParams(devices, lanes_per_device, host_lanes, window, eager, 0, kernel_ns, kernel_ns_per_kelem,
+                     copy_ns, copy_ns_per_kelem, inter_node_ns, alloc_ns, free_ns)
+
+
+class OooSimulation:
+    """The out-of-order engine simulated over the graphs of several contexts
+    (ig_ooo_*): one workgroup per graph, one launch for all."""
+
+    def __init__(self, contexts: Sequence[Context], params: OooParams):
+        self.L = contexts[0].L
+        self.n = len(contexts)
+        self.h = ctypes.c_void_p()
+        st = self.L.ig_ooo_create(_ctx_array(contexts), len(contexts), ctypes.byref(params), ctypes.byref(self.h))
+        if st != 0:
+            raise IgError("ig_ooo_create", st)
+
+    def run(self, stream=None) -> None:
+        st = self.L.ig_ooo_run(self.h, _stream_ptr(stream))
+        if st != 0:
+            raise IgError("ig_ooo_run", st)
+
+    def device_slots(self, i: int):
+        """(device address, count) of graph i's results."""
+        ptr, n = ctypes.c_void_p(), ctypes.c_uint64()
+        st = self.L.ig_ooo_slots(self.h, i, ctypes.byref(ptr), ctypes.byref(n))
+        if st != 0:
+            raise IgError("ig_ooo_slots", st)
+        return ptr.value, n.value
+
+    def fetch(self, i: int):
+        """(slots as OOO_SLOT_DTYPE, summary dict) of graph i."""
+        _, n = self.device_slots(i)
+        out = np.zeros(n, dtype=OOO_SLOT_DTYPE)
+        got = ctypes.c_size_t()
+        summ = OooSummary()
+        st = self.L.ig_ooo_fetch(self.h, i, out.ctypes.data if n else None, n, ctypes.byref(got), ctypes.byref(summ))
+        if st != 0:
+            raise IgError(f"ig_ooo_fetch (graph {i})", st)
+        return out, {k: getattr(summ, k) for k, _ in OooSummary._fields_}
+
+    def close(self) -> None:
+        if self.h:
+            self.L.ig_ooo_destroy(self.h)
+            self.h = ctypes.c_void_p()
 
     def __del__(self):
         try:

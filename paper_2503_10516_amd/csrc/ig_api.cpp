@@ -1029,4 +1029,133 @@ ig_status ig_stats_get(ig_context* c, ig_stats* out) {
     return IG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Out-of-order engine simulation (Sec. 4.1) over the contexts' graphs.
+// ---------------------------------------------------------------------------
+struct ig_ooo {
+    ig_ooo_params p;
+    std::vector<OooGraph> g;  // host view (device pointers)
+    OooGraph* dg;             // device array
+    ig_ooo_summary* dsum;
+    i32* dstatus;
+    char* mem;                // one device allocation for all of the above
+    u64 max_n, max_ne;
+    void* stream;             // of the last run
+    bool ran;
+};
+
+static bool ooo_params_ok(const ig_ooo_params* p) {
+    if (!p || p->lanes_per_device == 0 || p->host_lanes == 0 || p->window == 0 || p->window > IG_OOO_MAX_WINDOW ||
+        p->eager > 1)
+        return false;
+    if ((u64)p->devices * p->lanes_per_device + p->host_lanes > IG_OOO_MAX_LANES) return false;
+    return p->kernel_ns && p->copy_ns && p->alloc_ns && p->free_ns;
+}
+
+static u64 al256(u64 b) { return (b + 255) & ~(u64)255; }
+
+ig_status ig_ooo_create(ig_context* const* ctxs, size_t n, const ig_ooo_params* p, ig_ooo** out) {
+    if (!out) return IG_E_INVALID;
+    *out = nullptr;
+    if (!ctxs || n == 0 || n > 65535 || !ooo_params_ok(p)) return IG_E_INVALID;
+    u64 bytes = al256(n * sizeof(OooGraph)) + al256(n * sizeof(ig_ooo_summary)) + al256(n * sizeof(i32));
+    for (size_t i = 0; i < n; ++i) {
+        if (!ctxs[i]) return IG_E_INVALID;
+        const ig_status st = refresh(ctxs[i]);
+        if (st != IG_OK) return st;
+        const Scalars& sc = ctxs[i]->s;
+        if (sc.error || sc.n_instr > 0x7FFFFFFFull || sc.n_edges > 0xFFFFFFFFull) return IG_E_INVALID;
+        const u64 m = sc.n_instr, e = sc.n_edges;
+        bytes += al256(m * sizeof(ig_ooo_slot)) + 2 * al256((m + 1) * 4) + al256(e * 4) + 2 * al256(m * 4) +
+                 al256(m * 8);
+    }
+    ig_ooo* o = new ig_ooo();
+    o->p = *p;
+    if (igrt::dev_malloc((void**)&o->mem, bytes) != 0) {
+        delete o;
+        return IG_E_DEVICE;
+    }
+    char* cur = o->mem;
+    auto take = [&](u64 b) {
+        char* r = cur;
+        cur += al256(b);
+        return r;
+    };
+    o->dg = (OooGraph*)take(n * sizeof(OooGraph));
+    o->dsum = (ig_ooo_summary*)take(n * sizeof(ig_ooo_summary));
+    o->dstatus = (i32*)take(n * sizeof(i32));
+    o->g.resize(n);
+    for (size_t i = 0; i < n; ++i) {
+        const ig_context* c = ctxs[i];
+        OooGraph& g = o->g[i];
+        std::memset(&g, 0, sizeof g);
+        g.kind = c->h.i_kind;
+        g.flags = c->h.i_flags;
+        g.mem = c->h.i_mem;
+        g.box = c->h.i_box;
+        g.e_from = c->h.e_from;
+        g.e_to = c->h.e_to;
+        g.box_stride = c->h.cap_instr;
+        g.n = (u32)c->s.n_instr;
+        g.ne = (u32)c->s.n_edges;
+        g.sum = o->dsum + i;
+        g.status = o->dstatus + i;
+        g.out = (ig_ooo_slot*)take((u64)g.n * sizeof(ig_ooo_slot));
+        g.in_off = (u32*)take(((u64)g.n + 1) * 4);
+        g.out_off = (u32*)take(((u64)g.n + 1) * 4);
+        g.out_adj = (u32*)take((u64)g.ne * 4);
+        g.next = (u32*)take((u64)g.n * 4);
+        g.cls = (u32*)take((u64)g.n * 4);
+        g.dur = (u64*)take((u64)g.n * 8);
+        o->max_n = std::max<u64>(o->max_n, g.n);
+        o->max_ne = std::max<u64>(o->max_ne, g.ne);
+    }
+    if (igrt::copy_h2d(o->dg, o->g.data(), n * sizeof(OooGraph), nullptr) != 0 || igrt::stream_sync(nullptr) != 0) {
+        igrt::dev_free(o->mem);
+        delete o;
+        return IG_E_DEVICE;
+    }
+    *out = o;
+    return IG_OK;
+}
+
+ig_status ig_ooo_run(ig_ooo* o, void* stream) {
+    if (!o) return IG_E_INVALID;
+    if (igrt::memset_d(o->dstatus, 0, o->g.size() * sizeof(i32), stream) != 0) return IG_E_DEVICE;
+    if (igrt::launch_ooo(o->dg, (unsigned)o->g.size(), o->max_n, o->max_ne, &o->p, stream) != 0) return IG_E_DEVICE;
+    o->stream = stream;
+    o->ran = true;
+    return IG_OK;
+}
+
+ig_status ig_ooo_slots(ig_ooo* o, size_t i, ig_ooo_slot** d_slots, uint64_t* n) {
+    if (!o || i >= o->g.size() || !d_slots) return IG_E_INVALID;
+    *d_slots = o->g[i].out;
+    if (n) *n = o->g[i].n;
+    return IG_OK;
+}
+
+ig_status ig_ooo_fetch(ig_ooo* o, size_t i, ig_ooo_slot* dst, size_t cap, size_t* n_out, ig_ooo_summary* sum) {
+    if (!o || i >= o->g.size() || (!dst && cap) || !o->ran) return IG_E_INVALID;
+    const OooGraph& g = o->g[i];
+    i32 st = 0;
+    ig_ooo_summary hs;
+    const size_t m = std::min<size_t>(cap, g.n);
+    if (igrt::stream_sync(o->stream) != 0 || igrt::copy_d2h(&st, g.status, sizeof st, o->stream) != 0 ||
+        igrt::copy_d2h(&hs, g.sum, sizeof hs, o->stream) != 0 ||
+        (m && igrt::copy_d2h(dst, g.out, m * sizeof(ig_ooo_slot), o->stream) != 0) || igrt::stream_sync(o->stream) != 0)
+        return IG_E_DEVICE;
+    if (sum) *sum = hs;
+    if (n_out) *n_out = m;
+    return st;
+}
+
+ig_status ig_ooo_destroy(ig_ooo* o) {
+    if (!o) return IG_E_INVALID;
+    if (o->ran) igrt::stream_sync(o->stream);
+    igrt::dev_free(o->mem);
+    delete o;
+    return IG_OK;
+}
+
 }  // extern "C"

@@ -73,6 +73,12 @@ inline unsigned atomicMax(unsigned* p, unsigned v) {
     }
     return cur;
 }
+inline unsigned long long atomicMin(unsigned long long* p, unsigned long long v) {
+    unsigned long long cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (cur > v && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+    }
+    return cur;
+}
 inline unsigned atomicCAS(unsigned* p, unsigned cmp, unsigned v) {
     __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
     return cmp;
@@ -339,6 +345,30 @@ struct DevStats {
     unsigned long long per_dep[5];
 };
 
+// One graph of an out-of-order engine simulation (ig_ooo.hip).
+struct OooGraph {
+    // records of the context (device arrays)
+    const u8* kind;
+    const u8* flags;
+    const u16* mem;
+    const i64* box;   // [6][box_stride]
+    const u32* e_from;
+    const u32* e_to;
+    u64 box_stride;
+    u32 n, ne;
+    // results
+    ig_ooo_slot* out;     // [n]
+    ig_ooo_summary* sum;  // [1]
+    i32* status;          // [1]
+    // workspace
+    u32* in_off;   // [n + 1] first edge of each target
+    u32* out_off;  // [n + 1] successor list offsets (counts before the scan)
+    u32* out_adj;  // [ne]
+    u32* next;     // [n] lane FIFO links (fill cursors during preparation)
+    u32* cls;      // [n] lanes [lo, hi) as lo | hi << 16; lo == hi: the engine's own
+    u64* dur;      // [n]
+};
+
 }  // namespace igd
 
 // Launch glue implemented next to the kernels (ig_kernels.hip).
@@ -367,6 +397,9 @@ int launch_pack_instructions(const igd::DevCtx* dev_ctx, uint64_t first, uint64_
                              void* stream);
 int launch_pack_bindings(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_binding* out_dev, void* stream);
 int launch_pack_edges(const igd::DevCtx* dev_ctx, uint64_t first, uint64_t n, ig_edge* out_dev, void* stream);
+// the out-of-order engine over n_graphs graphs (device array d_graphs); max_n / max_ne size the preparation grids
+int launch_ooo(const igd::OooGraph* d_graphs, unsigned n_graphs, uint64_t max_n, uint64_t max_ne, const ig_ooo_params* p,
+               void* stream);
 int launch_stats(const igd::DevCtx* dev_ctx, uint64_t n_instr, uint64_t n_bind, uint64_t n_edge,
                  igd::DevStats* out_dev, void* stream);
 // Events (completion of work queued on a stream) and a side stream.

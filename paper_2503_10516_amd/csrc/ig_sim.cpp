@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "ig_kernels.hip"
+#include "ig_ooo.hip"
 
 unsigned long long ig_clock() {
     return (unsigned long long)std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -155,6 +156,42 @@ int graph_launch(void* exec, void* stream) {
 }
 int graph_destroy(void* exec) {
     delete (SimGraph*)exec;
+    return 0;
+}
+
+// The engine simulation: preparation as plain loops, then each graph's
+// engine in one emulated workgroup.
+int launch_ooo(const igd::OooGraph* gs, unsigned n_graphs, uint64_t, uint64_t, const ig_ooo_params* p, void*) {
+    for (unsigned b = 0; b < n_graphs; ++b) {
+        const igd::OooGraph& g = gs[b];
+        igd::ooo_prep_tail(g);
+        for (uint32_t x = 0; x < g.n; ++x) igd::ooo_prep_node(g, *p, x);
+        for (uint32_t e = 0; e < g.ne; ++e) igd::ooo_prep_edge(g, e);
+    }
+    const unsigned threads = 64;
+    for (unsigned b = 0; b < n_graphs; ++b) {
+        for (int phase = 0; phase < 2; ++phase) {
+            igd::OooShared* sh = new igd::OooShared();
+            std::vector<uint32_t> part(threads);
+            igsim::Barrier gate;
+            gate.n = threads;
+            for (int& l : gate.line) l = -1;
+            std::vector<std::thread> ts;
+            for (unsigned t = 0; t < threads; ++t)
+                ts.emplace_back([=, &gate, &part] {
+                    igsim::cur.tid = t;
+                    igsim::cur.nthreads = threads;
+                    igsim::cur.block = b;
+                    igsim::cur.bar = &gate;
+                    if (phase == 0) igd::ooo_scan(gs[b], part.data());
+                    else igd::ooo_engine(gs[b], *p, *sh);
+                });
+            for (auto& t : ts) t.join();
+            delete sh;
+            if (phase == 0)
+                for (uint32_t e = 0; e < gs[b].ne; ++e) igd::ooo_fill_edge(gs[b], e);
+        }
+    }
     return 0;
 }
 

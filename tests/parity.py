@@ -109,3 +109,37 @@ def big_read_stream(variant):
             s.epoch()
     s.shutdown()
     return s
+
+
+# --- the out-of-order engine simulation (Sec. 4.1) ---
+
+OOO_PARAMS = [
+    dict(lanes_per_device=1, host_lanes=1, window=1),
+    dict(lanes_per_device=2, host_lanes=2, window=16),
+    dict(lanes_per_device=3, host_lanes=1, window=1024, eager=0),
+    dict(lanes_per_device=2, host_lanes=3, window=7),
+    dict(lanes_per_device=4, host_lanes=2, window=4096, kernel_ns=1, copy_ns=1, alloc_ns=1, free_ns=1,
+         kernel_ns_per_kelem=0, copy_ns_per_kelem=0, inter_node_ns=0),
+]
+
+
+def ooo_against_oracle(streams, contexts, kw, oracle_outs=None):
+    """Simulate the engine over the contexts' graphs (one launch) and over
+    the oracle's graphs of the same streams; every slot and summary must be
+    equal (integer output: no tolerance)."""
+    import oracle
+    from paper_2503_10516_amd import binding as B
+    devs = max(s.nodes * s.devices for s in streams)
+    sim = B.OooSimulation(contexts, B.ooo_params(devs, **kw))
+    sim.run()
+    try:
+        for i, s in enumerate(streams):
+            o = oracle_outs[i] if oracle_outs is not None else oracle.run_stream(s)
+            want, wsum = oracle.ooo_simulate(o["instructions"], o["edges"], oracle.ooo_params(devs, **kw))
+            got, gsum = sim.fetch(i)
+            assert len(got) == len(want), (s.name, len(got), len(want))
+            j = first_difference(want, got)
+            assert j is None, f"{s.name} {kw}: slot {j} differs: oracle {want[j]} hip {got[j]}"
+            assert gsum == wsum, (s.name, kw, gsum, wsum)
+    finally:
+        sim.close()

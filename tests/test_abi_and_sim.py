@@ -14,7 +14,7 @@ import subprocess
 import pytest
 
 import oracle
-from parity import assert_same, big_read_stream, reader_run_stream
+from parity import OOO_PARAMS, assert_same, big_read_stream, ooo_against_oracle, reader_run_stream
 from paper_2503_10516_amd import binding as B
 from paper_2503_10516_amd import streams as S
 
@@ -48,7 +48,7 @@ def test_hip_library_exports_every_declared_symbol():
 
 
 def _sources():
-    return [os.path.join(CSRC, f) for f in ("ig_sim.cpp", "ig_api.cpp", "ig_kernels.hip", "ig_dev.h")] + \
+    return [os.path.join(CSRC, f) for f in ("ig_sim.cpp", "ig_api.cpp", "ig_kernels.hip", "ig_ooo.hip", "ig_dev.h")] + \
         [os.path.join(ROOT, "include", "ig.h")]
 
 
@@ -332,3 +332,51 @@ def test_sim_progress_noalloc_equals_progress(sim_lib):
         B.IG_E_CAPACITY
     for c in ctxs:
         c.close()
+
+
+def _ooo_streams():
+    from test_oracle_semantics import tdag_stream
+    return [S.nbody_example(), S.stencil_1d(n=256, tasks=24), S.nbody(n=64, steps=3, nodes=2, devices=2, chunks=8),
+            S.random_small(3), tdag_stream(5), S.growing(width=24, steps=16, devices=4)]
+
+
+@pytest.mark.parametrize("kw", OOO_PARAMS, ids=[f"p{i}" for i in range(len(OOO_PARAMS))])
+def test_sim_ooo_engine_equals_oracle(kw, sim_lib):
+    """The engine kernel (one emulated workgroup per graph, all graphs in one
+    launch) assigns every instruction to the lane, at the moments, the
+    oracle's engine does, under each parameter set."""
+    streams = _ooo_streams()
+    ctxs = []
+    for s in streams:
+        ctx = B.make_context(s, lib_path=sim_lib, threads=64)
+        ctx.record(s)
+        ctx.flush()
+        assert ctx.sync() == 0
+        ctxs.append(ctx)
+    try:
+        ooo_against_oracle(streams, ctxs, kw)
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+def test_sim_ooo_rejects_bad_parameters_and_lanes(sim_lib):
+    s = S.nbody_example()
+    ctx = B.make_context(s, lib_path=sim_lib, threads=64)
+    ctx.record(s)
+    ctx.flush()
+    assert ctx.sync() == 0
+    try:
+        for kw in (dict(window=0), dict(window=4097), dict(lanes_per_device=0), dict(host_lanes=0), dict(eager=2),
+                   dict(kernel_ns=0), dict(lanes_per_device=600)):
+            with pytest.raises(B.IgError):
+                B.OooSimulation([ctx], B.ooo_params(2, **kw))
+        # too few device lanes for the graph's memories: the graph's status
+        sim = B.OooSimulation([ctx], B.ooo_params(1))
+        sim.run()
+        with pytest.raises(B.IgError) as e:
+            sim.fetch(0)
+        assert e.value.status == B.IG_E_INVALID
+        sim.close()
+    finally:
+        ctx.close()
