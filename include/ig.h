@@ -478,7 +478,7 @@ ig_status ig_stats_get(ig_context* ctx, ig_stats* out);
  * not seen until the handle is created again.
  * --------------------------------------------------------------------------- */
 #define IG_OOO_MAX_WINDOW 4096u
-#define IG_OOO_MAX_LANES 1024u  /* devices * lanes_per_device + host_lanes */
+#define IG_OOO_MAX_LANES 1023u  /* devices * lanes_per_device + host_lanes */
 #define IG_OOO_ENGINE 0u        /* horizon / epoch: completed by the engine */
 #define IG_OOO_DIRECT 1u
 #define IG_OOO_EAGER 2u
@@ -518,8 +518,8 @@ typedef struct ig_ooo_summary {
 typedef struct ig_ooo ig_ooo;
 /* A simulation handle over the graphs of n contexts (synchronises each
  * context's stream to read its record counts).  Allocates device memory for
- * the per-instruction results and a workspace of 28 bytes per instruction
- * and 4 per edge.  Errors: IG_E_INVALID (parameters out of range, a context
+ * the per-instruction results (32 bytes each) and a workspace of 44 bytes
+ * per instruction and 12 per edge.  Errors: IG_E_INVALID (parameters out of range, a context
  * with an analysis error, more than 2^31 - 1 instructions), IG_E_DEVICE. */
 ig_status ig_ooo_create(ig_context* const* ctxs, size_t n, const ig_ooo_params* p, ig_ooo** out);
 /* Queue the simulation of every graph on `stream` (asynchronous). */

@@ -73,6 +73,12 @@ inline unsigned atomicMax(unsigned* p, unsigned v) {
     }
     return cur;
 }
+inline unsigned long long atomicMax(unsigned long long* p, unsigned long long v) {
+    unsigned long long cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (cur < v && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+    }
+    return cur;
+}
 inline unsigned long long atomicMin(unsigned long long* p, unsigned long long v) {
     unsigned long long cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
     while (cur > v && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
@@ -115,6 +121,23 @@ __device__ __forceinline__ unsigned long long ig_clock() { return wall_clock64()
 __device__ __forceinline__ unsigned ig_shfl_up(unsigned v, unsigned delta) { return __shfl_up(v, delta, 64); }
 #define IGD __device__ __forceinline__
 #define IGN __device__ __noinline__
+#endif
+
+// A device pointer known to address global memory.  Pointers that kernels
+// read out of descriptors are generic, so their accesses compile to flat
+// instructions, which also count against the LDS wait counter: every LDS
+// wait after them would wait for global memory too.  gmem(p)[i] compiles to
+// global loads and stores instead.
+#ifdef IG_HOST_SIM
+template <class T>
+inline T* gmem(T* p) {
+    return p;
+}
+#else
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
 #endif
 
 namespace igd {
@@ -345,6 +368,17 @@ struct DevStats {
     unsigned long long per_dep[5];
 };
 
+// A successor y with its dependency list [k0, k1) (edges sorted by target).
+struct OooSucc {
+    u32 y, k0, k1;
+};
+// Per instruction while it is in flight: the next instruction on its lane
+// and that one's end, and its own successor list (offset, length).
+struct OooRec {
+    u32 next, o0, deg, pad;
+    u64 next_end;
+};
+
 // One graph of an out-of-order engine simulation (ig_ooo.hip).
 struct OooGraph {
     // records of the context (device arrays)
@@ -363,9 +397,9 @@ struct OooGraph {
     // workspace
     u32* in_off;   // [n + 1] first edge of each target
     u32* out_off;  // [n + 1] successor list offsets (counts before the scan)
-    u32* out_adj;  // [ne]
-    u32* next;     // [n] lane FIFO links (fill cursors during preparation)
-    u32* cls;      // [n] lanes [lo, hi) as lo | hi << 16; lo == hi: the engine's own
+    OooSucc* out_adj;  // [ne] successors with their dependency-list ranges
+    OooRec* rec;   // [n] lane FIFO links and successor ranges (fill cursors during preparation)
+    u32* cls;      // [n] lane class
     u64* dur;      // [n]
 };
 

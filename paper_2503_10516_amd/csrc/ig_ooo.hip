@@ -24,32 +24,113 @@
 //     and at most one instruction per lane completes at a moment.
 #include "ig_dev.h"
 
+// Per-phase clock totals of the engine's first thread, printed at the end
+// (profiling builds only, -DOOO_PROF).
+#ifdef OOO_PROF
+#include <cstdio>
+#define OOO_PROF_DECL u64 prof_t[6] = {0, 0, 0, 0, 0, 0}, prof_last = wall_clock64()
+#define OOO_PROF_MARK(k)                    \
+    do {                                    \
+        const u64 now_ = wall_clock64();    \
+        prof_t[k] += now_ - prof_last;      \
+        prof_last = now_;                   \
+    } while (0)
+#define OOO_PROF_REPORT                                                                                         \
+    printf("ooo prof n=%u: wait %llu assign %llu prop %llu | wait %llu min+pop %llu prop %llu (wall ticks)\n", n, \
+           prof_t[0], prof_t[1], prof_t[2], prof_t[3], prof_t[4], prof_t[5])
+#else
+#define OOO_PROF_DECL (void)0
+#define OOO_PROF_MARK(k) (void)0
+#define OOO_PROF_REPORT (void)0
+#endif
+
 namespace igd {
 
 constexpr u32 OOO_WR = IG_OOO_MAX_WINDOW;  // ring slots, a power of two
 constexpr u32 OOO_WORDS = OOO_WR / 64;     // 64: one summary word covers the ring
 constexpr u32 OOO_MAXL = IG_OOO_MAX_LANES;
-constexpr u32 OOO_WIDE = 64;               // successor lists longer than this are walked by all threads
-constexpr u32 OOO_WIDE_BIT = 0x80000000u;
 constexpr u64 OOO_INF = ~0ull;
+constexpr u32 OOO_LANE_SHIFT = 11;         // e_cls: class (11 bits) | eager lane + 1
+static_assert(OOO_MAXL < 2048, "classes fit the packed class word");
 static_assert(OOO_WORDS == 64, "the take summary is one 64-bit word");
 
-struct OooShared {
-    u64 take[OOO_WORDS];  // ring bitmap: assignable at the start of the next round
-    u64 asg[OOO_WORDS];   // ring bitmap: assigned, for ids in [first, first + ring)
-    u64 busy[OOO_MAXL];   // when each lane frees up
-    u64 head_end[OOO_MAXL];
-    u32 head[OOO_MAXL], tail[OOO_MAXL];
-    u64 e_dur[OOO_WR];    // per taken slot: duration, lane class, eager lane + 1 (0: direct)
-    u32 e_cls[OOO_WR];
-    u16 e_lane[OOO_WR];
-    u32 done[OOO_WR];     // whose successors are evaluated next (OOO_WIDE_BIT: by all threads)
-    u64 take_sum[2];      // non-empty words of take[], by loop-iteration parity (the
-                          // next iteration's word is filled while this one's is read)
-    u64 tmin[2];          // the next completion, by loop-iteration parity
-    u64 t;
-    u32 n_done, first, win_lo, win_hi;
+// An in-order lane: when it frees up, and its FIFO of in-flight
+// instructions (head, tail; linked through the workspace), read and written
+// whole.
+struct OooLane {
+    u64 busy;
+    u64 head_end;
+    u32 head, tail;
+    u64 pad;
 };
+
+struct OooShared {
+    u64 take[2][OOO_WORDS];  // ring bitmaps by loop-iteration parity: assignable at the
+                             // start of the round that reads them
+    u64 asg[OOO_WORDS];      // ring bitmap: assigned, for ids in [first, first + ring)
+    OooLane lane[OOO_MAXL];
+    // per taken slot: duration; class | (eager lane + 1) << 11; successor
+    // list (offset, length)
+    u64 e_dur[OOO_WR];
+    u32 e_cls[OOO_WR];
+    u32 e_o0[OOO_WR];
+    u32 e_deg[OOO_WR];
+    // changed instructions whose successors are evaluated next: successor
+    // list offset and position in the concatenation of the lists
+    u32 d_o0[OOO_WR];
+    u32 d_pre[OOO_WR];
+    // by loop-iteration parity (one is read while the other is prepared):
+    u64 take_sum[2];   // non-empty words of take[]
+    u64 tmin[2];       // the next completion
+    u64 cnt[2];        // changed entries << 32 | their successors in total
+    u32 firstp[2];     // the first unassigned id
+    u64 t;
+    u32 win_lo, win_hi;
+    u64 r_direct, r_eager, r_makespan;
+};
+
+// Whole-record global accesses, field by field (a record behind a global
+// pointer has no copy operations of its own).
+IGD void ooo_put_slot(ig_ooo_slot* p, const ig_ooo_slot& o) {
+    auto q = gmem(p);
+    q->lane = o.lane;
+    q->how = o.how;
+    q->issue = o.issue;
+    q->start = o.start;
+    q->end = o.end;
+}
+IGD void ooo_put_succ(OooSucc* p, const OooSucc& v) {
+    auto q = gmem(p);
+    q->y = v.y;
+    q->k0 = v.k0;
+    q->k1 = v.k1;
+}
+IGD OooSucc ooo_get_succ(const OooSucc* p) {
+    auto q = gmem(p);
+    OooSucc v;
+    v.y = q->y;
+    v.k0 = q->k0;
+    v.k1 = q->k1;
+    return v;
+}
+IGD void ooo_put_rec(OooRec* p, const OooRec& v) {
+    auto q = gmem(p);
+    q->next = v.next;
+    q->o0 = v.o0;
+    q->deg = v.deg;
+    q->pad = v.pad;
+    q->next_end = v.next_end;
+}
+IGD OooRec ooo_get_rec(const OooRec* p) {
+    auto q = gmem(p);
+    OooRec v;
+    v.next = q->next;
+    v.o0 = q->o0;
+    v.deg = q->deg;
+    v.pad = q->pad;
+    v.next_end = q->next_end;
+    return v;
+}
 
 IGD void ooo_set_status(const OooGraph& g, i32 st) { atomicCAS((unsigned*)g.status, 0u, (unsigned)st); }
 
@@ -68,10 +149,10 @@ IGD u32 ooo_lower_bound(const u32* a, u32 n, u32 v) {
 IGD void ooo_prep_node(const OooGraph& g, const ig_ooo_params& p, u32 x) {
     u64 vol = 1;
     for (u32 d = 0; d < 3; ++d) {
-        const i64 lo = g.box[d * g.box_stride + x], hi = g.box[(3 + d) * g.box_stride + x];
+        const i64 lo = gmem(g.box)[d * g.box_stride + x], hi = gmem(g.box)[(3 + d) * g.box_stride + x];
         vol *= hi > lo ? (u64)(hi - lo) : 0ull;
     }
-    const u32 kind = g.kind[x], mem = g.mem[x];
+    const u32 kind = gmem(g.kind)[x], mem = gmem(g.mem)[x];
     u32 dev = NONE, cls = 0;
     u64 dur = 0;
     bool engine = false;
@@ -80,7 +161,7 @@ IGD void ooo_prep_node(const OooGraph& g, const ig_ooo_params& p, u32 x) {
         dur = p.kernel_ns + vol * p.kernel_ns_per_kelem / 1024;
     } else if (kind == IG_COPY) {
         dev = mem >= 2 ? mem : NONE;
-        dur = p.copy_ns + vol * p.copy_ns_per_kelem / 1024 + ((g.flags[x] & IG_F_INTER_NODE) ? p.inter_node_ns : 0);
+        dur = p.copy_ns + vol * p.copy_ns_per_kelem / 1024 + ((gmem(g.flags)[x] & IG_F_INTER_NODE) ? p.inter_node_ns : 0);
     } else if (kind == IG_ALLOC) {
         dur = p.alloc_ns;
     } else if (kind == IG_FREE) {
@@ -88,43 +169,43 @@ IGD void ooo_prep_node(const OooGraph& g, const ig_ooo_params& p, u32 x) {
     } else {
         engine = true;
     }
-    if (!engine) {
-        const u32 host0 = p.devices * p.lanes_per_device;
-        if (dev != NONE) {
-            if (dev < 2 || dev - 2 >= p.devices) {
-                ooo_set_status(g, IG_E_INVALID);
-                dev = 2;
-            }
-            const u32 lo = (dev - 2) * p.lanes_per_device;
-            cls = lo | (lo + p.lanes_per_device) << 16;
-        } else {
-            cls = host0 | (host0 + p.host_lanes) << 16;
+    // lane class: device d (lanes d * Q ..), the host lanes (class
+    // `devices`), or the engine itself (class devices + 1)
+    if (engine) {
+        cls = p.devices + 1;
+    } else if (dev != NONE) {
+        if (dev < 2 || dev - 2 >= p.devices) {
+            ooo_set_status(g, IG_E_INVALID);
+            dev = 2;
         }
+        cls = dev - 2;
+    } else {
+        cls = p.devices;
     }
-    g.cls[x] = cls;
-    g.dur[x] = dur;
-    g.in_off[x] = ooo_lower_bound(g.e_to, g.ne, x);
-    g.out_off[x] = 0;
+    gmem(g.cls)[x] = cls;
+    gmem(g.dur)[x] = dur;
+    gmem(g.in_off)[x] = ooo_lower_bound(g.e_to, g.ne, x);
+    gmem(g.out_off)[x] = 0;
     ig_ooo_slot s;
     s.lane = NONE;
     s.how = 0;
     s.issue = OOO_INF;
     s.start = 0;
     s.end = OOO_INF;
-    g.out[x] = s;
+    ooo_put_slot(g.out + x, s);
 }
 
 // The closing entries of the two offset arrays (one thread per graph).
 IGD void ooo_prep_tail(const OooGraph& g) {
-    g.in_off[g.n] = g.ne;
-    g.out_off[g.n] = 0;
+    gmem(g.in_off)[g.n] = g.ne;
+    gmem(g.out_off)[g.n] = 0;
 }
 
 // An edge the engine can use: ids in range, source before target, sorted
 // by target.
 IGD bool ooo_edge_ok(const OooGraph& g, u32 e) {
-    const u32 f = g.e_from[e], t = g.e_to[e];
-    return t < g.n && f < t && (e == 0 || g.e_to[e - 1] <= t);
+    const u32 f = gmem(g.e_from)[e], t = gmem(g.e_to)[e];
+    return t < g.n && f < t && (e == 0 || gmem(g.e_to)[e - 1] <= t);
 }
 
 // Preparation, one edge: the check and the successor count of its source.
@@ -133,7 +214,7 @@ IGD void ooo_prep_edge(const OooGraph& g, u32 e) {
         ooo_set_status(g, IG_E_INVALID);
         return;
     }
-    atomicAdd(&g.out_off[g.e_from[e]], 1u);
+    atomicAdd(&g.out_off[gmem(g.e_from)[e]], 1u);
 }
 
 // Preparation, one workgroup per graph: exclusive scan of the successor
@@ -144,7 +225,7 @@ IGD void ooo_scan(const OooGraph& g, u32* part) {
     const u32 seg = (m + nt - 1) / nt;
     const u32 lo = tid * seg < m ? tid * seg : m, hi = lo + seg < m ? lo + seg : m;
     u32 s = 0;
-    for (u32 i = lo; i < hi; ++i) s += g.out_off[i];
+    for (u32 i = lo; i < hi; ++i) s += gmem(g.out_off)[i];
     part[tid] = s;
     ig_barrier_at(__LINE__);
     if (tid == 0) {
@@ -158,132 +239,191 @@ IGD void ooo_scan(const OooGraph& g, u32* part) {
     ig_barrier_at(__LINE__);
     u32 acc = part[tid];
     for (u32 i = lo; i < hi; ++i) {
-        const u32 v = g.out_off[i];
-        g.out_off[i] = acc;
-        if (i < g.n) g.next[i] = acc;
+        const u32 v = gmem(g.out_off)[i];
+        gmem(g.out_off)[i] = acc;
+        if (i < g.n) gmem(g.rec)[i].next = acc;
         acc += v;
     }
 }
 
 IGD void ooo_fill_edge(const OooGraph& g, u32 e) {
     if (!ooo_edge_ok(g, e)) return;  // not counted either
-    const u32 pos = atomicAdd(&g.next[g.e_from[e]], 1u);
-    g.out_adj[pos] = g.e_to[e];
+    const u32 pos = atomicAdd(&g.rec[gmem(g.e_from)[e]].next, 1u);
+    const u32 y = gmem(g.e_to)[e];
+    OooSucc sc;
+    sc.y = y;
+    sc.k0 = gmem(g.in_off)[y];
+    sc.k1 = gmem(g.in_off)[y + 1];
+    ooo_put_succ(g.out_adj + pos, sc);
+}
+
+// The lanes [lo, hi) of a class (lo == hi: the engine's own).
+IGD void ooo_lanes(const ig_ooo_params& p, u32 cls, u32& lo, u32& hi) {
+    const u32 host0 = p.devices * p.lanes_per_device;
+    if (cls < p.devices) {
+        lo = cls * p.lanes_per_device;
+        hi = lo + p.lanes_per_device;
+    } else if (cls == p.devices) {
+        lo = host0;
+        hi = host0 + p.host_lanes;
+    } else {
+        lo = hi = 0;
+    }
 }
 
 // Is y assignable at time t (all dependencies complete, or with eager all
 // incomplete ones on one lane of y's class)?  If so, mark it for the next
-// round (its non-empty word in *tsum).  Called for any id; filters itself.
-IGD void ooo_eval(const OooGraph& g, OooShared& sh, u32 eager, u32 y, u64 t, u32 first, u32 win_end, u64* tsum) {
+// round (its non-empty word in *tsum) with what the assignment and the
+// following propagation need.  Called for any id; filters itself.  The
+// dependencies are read four at a time so that their loads overlap.
+IGD void ooo_eval(const OooGraph& g, OooShared& sh, const ig_ooo_params& p, u32 y, u32 k0, u32 k1, u64 t, u32 first,
+                  u32 win_end, u64* take, u64* tsum) {
     if (y < first || y >= win_end) return;
     const u32 s = y & (OOO_WR - 1);
     if ((sh.asg[s >> 6] >> (s & 63)) & 1ull) return;
-    const u32 cls = g.cls[y];
-    const u32 lo = cls & 0xFFFFu, hi = cls >> 16;
+    const u32 cls = gmem(g.cls)[y];
+    const u32 o0 = gmem(g.out_off)[y], o1 = gmem(g.out_off)[y + 1];
+    const u64 dur = gmem(g.dur)[y];
+    u32 lo, hi;
+    ooo_lanes(p, cls, lo, hi);
+    const u32 eager = p.eager;
     u32 L = NONE;
-    for (u32 k = g.in_off[y], ke = g.in_off[y + 1]; k < ke; ++k) {
-        const ig_ooo_slot& d = g.out[g.e_from[k]];
-        if (d.end <= t) continue;
-        // incomplete (or unassigned: lane NONE, end infinite)
-        if (!eager || lo == hi) return;
-        const u32 l = d.lane;
-        if (l < lo || l >= hi || (L != NONE && l != L)) return;
-        L = l;
+    for (u32 k = k0; k < k1; k += 4) {
+        u32 d[4];
+#pragma unroll
+        for (u32 q = 0; q < 4; ++q) d[q] = k + q < k1 ? gmem(g.e_from)[k + q] : NONE;
+        u64 end[4];
+        u32 lane[4];
+#pragma unroll
+        for (u32 q = 0; q < 4; ++q) {
+            end[q] = d[q] != NONE ? gmem(g.out)[d[q]].end : 0ull;
+            lane[q] = d[q] != NONE ? gmem(g.out)[d[q]].lane : NONE;
+        }
+#pragma unroll
+        for (u32 q = 0; q < 4; ++q) {
+            if (end[q] <= t) continue;
+            // incomplete (or unassigned: lane NONE, end infinite)
+            if (!eager || lo == hi) return;
+            if (lane[q] < lo || lane[q] >= hi || (L != NONE && lane[q] != L)) return;
+            L = lane[q];
+        }
     }
-    sh.e_cls[s] = cls;
-    sh.e_dur[s] = g.dur[y];
-    sh.e_lane[s] = (u16)(L == NONE ? 0u : L + 1);
+    sh.e_cls[s] = cls | (L == NONE ? 0u : (L + 1) << OOO_LANE_SHIFT);
+    sh.e_dur[s] = dur;
+    sh.e_o0[s] = o0;
+    sh.e_deg[s] = o1 - o0;
     const u64 bit = 1ull << (s & 63);
-    const u64 old = atomicOr(&sh.take[s >> 6], bit);
+    const u64 old = atomicOr(&take[s >> 6], bit);
     if (!(old & bit)) atomicOr(tsum, 1ull << (s >> 6));
 }
 
-// Evaluate the successors of sh.done[0 .. n_done) and the ids newly in the
-// window [win_lo, win_hi); what became assignable is marked in take[] and
-// *tsum.
-IGD void ooo_propagate(const OooGraph& g, OooShared& sh, u32 eager, u32 window, u64* tsum) {
+// Evaluate the successors of the changed instructions (cnt: entries << 32
+// | successors; entry i: successor list from d_o0[i], at position d_pre[i]
+// of the concatenation; one thread per successor) and the ids newly in the
+// window [win_lo, win_hi); marks go to take / tsum.
+IGD void ooo_propagate(const OooGraph& g, OooShared& sh, const ig_ooo_params& p, u64 cnt, u32 first, u64* take,
+                       u64* tsum) {
     const u32 tid = ig_tid(), nt = ig_nthreads();
     const u64 t = sh.t;
-    const u32 first = sh.first;
-    const u32 win_end = (u64)first + window < g.n ? first + window : g.n;
-    const u32 nd = sh.n_done;
-    for (u32 i = tid; i < nd; i += nt) {
-        const u32 x = sh.done[i];
-        const u32 o0 = g.out_off[x], o1 = g.out_off[x + 1];
-        if (o1 - o0 > OOO_WIDE) {
-            sh.done[i] = x | OOO_WIDE_BIT;
-            continue;
+    const u32 win_end = (u64)first + p.window < g.n ? first + p.window : g.n;
+    const u32 nd = (u32)(cnt >> 32), total = (u32)cnt;
+    for (u32 j = tid; j < total; j += nt) {
+        u32 lo = 0, hi = nd;  // the last entry starting at or before j
+        while (hi - lo > 1) {
+            const u32 mid = (lo + hi) >> 1;
+            if (sh.d_pre[mid] <= j) lo = mid;
+            else hi = mid;
         }
-        for (u32 j = o0; j < o1; ++j) ooo_eval(g, sh, eager, g.out_adj[j], t, first, win_end, tsum);
+        const OooSucc sc = ooo_get_succ(g.out_adj + sh.d_o0[lo] + (j - sh.d_pre[lo]));
+        ooo_eval(g, sh, p, sc.y, sc.k0, sc.k1, t, first, win_end, take, tsum);
     }
-    for (u32 y = sh.win_lo + tid; y < sh.win_hi; y += nt) ooo_eval(g, sh, eager, y, t, first, win_end, tsum);
-    ig_barrier_at(__LINE__);
-    for (u32 i = 0; i < nd; ++i) {
-        const u32 xw = sh.done[i];
-        if (!(xw & OOO_WIDE_BIT)) continue;
-        const u32 x = xw & ~OOO_WIDE_BIT;
-        const u32 o0 = g.out_off[x], o1 = g.out_off[x + 1];
-        for (u32 j = o0 + tid; j < o1; j += nt) ooo_eval(g, sh, eager, g.out_adj[j], t, first, win_end, tsum);
-    }
+    for (u32 y = sh.win_lo + tid; y < sh.win_hi; y += nt)
+        ooo_eval(g, sh, p, y, gmem(g.in_off)[y], gmem(g.in_off)[y + 1], t, first, win_end, take, tsum);
 }
 
 // The engine, one workgroup per graph.
 IGD void ooo_engine(const OooGraph& g, const ig_ooo_params& p, OooShared& sh) {
     const u32 tid = ig_tid(), nt = ig_nthreads();
-    const u32 n = g.n, W = p.window, eager = p.eager;
+    const u32 n = g.n, W = p.window;
     const u32 n_lanes = p.devices * p.lanes_per_device + p.host_lanes;
-    for (u32 w = tid; w < OOO_WORDS; w += nt) sh.take[w] = sh.asg[w] = 0;
+    const u32 n_cls = p.devices + 2;
+    for (u32 w = tid; w < OOO_WORDS; w += nt) sh.take[0][w] = sh.take[1][w] = sh.asg[w] = 0;
     for (u32 l = tid; l < OOO_MAXL; l += nt) {
-        sh.busy[l] = 0;
-        sh.head_end[l] = OOO_INF;
-        sh.head[l] = sh.tail[l] = NONE;
+        OooLane z;
+        z.busy = 0;
+        z.head_end = OOO_INF;
+        z.head = z.tail = NONE;
+        z.pad = 0;
+        sh.lane[l] = z;
     }
     if (tid == 0) {
-        sh.take_sum[0] = sh.take_sum[1] = 0;
+        for (u32 q = 0; q < 2; ++q) {
+            sh.take_sum[q] = 0;
+            sh.tmin[q] = OOO_INF;
+            sh.cnt[q] = 0;
+            sh.firstp[q] = 0;
+        }
         sh.t = 0;
-        sh.first = 0;
-        sh.n_done = 0;
         sh.win_lo = 0;
         sh.win_hi = W < n ? W : n;
-        sh.tmin[0] = sh.tmin[1] = OOO_INF;
+        sh.r_direct = sh.r_eager = sh.r_makespan = 0;
     }
     ig_barrier_at(__LINE__);
     const bool bad = *(volatile i32*)g.status != 0;
     u64 steps = n ? 1 : 0, rounds = 0, direct = 0, n_eager = 0, makespan = 0;
     bool stalled = false;
+    OOO_PROF_DECL;
     if (!bad && n) {
-        ooo_propagate(g, sh, eager, W, &sh.take_sum[0]);
+        ooo_propagate(g, sh, p, 0, 0, sh.take[0], &sh.take_sum[0]);
         ig_barrier_at(__LINE__);
+        // Iteration `it` reads the state of parity it & 1 and prepares that
+        // of parity (it + 1) & 1, which nobody reads during the iteration.
         for (u32 it = 0;; ++it) {
-            // this iteration's round was marked under parity it & 1; the
-            // next one is marked under the other parity, which the assigning
-            // thread clears before the barrier that precedes the marking
-            u64* next_sum = &sh.take_sum[(it + 1) & 1];
-            const u64 summ = sh.take_sum[it & 1];
+            const u32 cur = it & 1, nxt = cur ^ 1;
+            const u64 summ = sh.take_sum[cur];
+            const u32 first0 = sh.firstp[cur];
             if (summ) {
-                if (tid == 0) {
-                    *next_sum = 0;
-                    sh.tmin[(it + 1) & 1] = OOO_INF;
-                    const u64 t = sh.t;
-                    const u32 first0 = sh.first;
-                    const u32 fs = first0 & (OOO_WR - 1), w0 = fs >> 6, b0 = fs & 63;
-                    u32 nd = 0;
-                    // ring order from `first`: word w0 from bit b0, the words
-                    // after it, then word w0 below bit b0
-                    for (u32 step = 0; step <= OOO_WORDS; ++step) {
-                        const u32 w = (w0 + step) & (OOO_WORDS - 1);
-                        if (!((summ >> w) & 1ull)) continue;
-                        u64 bits = sh.take[w];
-                        if (step == 0) bits &= ~0ull << b0;
-                        else if (step == OOO_WORDS) bits &= b0 ? (1ull << b0) - 1 : 0ull;
-                        sh.take[w] &= ~bits;
+                OOO_PROF_MARK(0);
+                const u64 t = sh.t;
+                const u32 fs = first0 & (OOO_WR - 1), w0 = fs >> 6, b0 = fs & 63;
+                const u64* tk = sh.take[cur];
+                // the round: each class's instructions in id order, one
+                // thread per class (classes share no lane); ring order from
+                // `first`: word w0 from bit b0, the words after it, then
+                // word w0 below bit b0
+                // the non-empty words in ring order: rotated so that bit i is
+                // word w0 + i; word w0 comes again at the end (bits below b0)
+                const u64 rot = w0 ? (summ >> w0) | (summ << (OOO_WORDS - w0)) : summ;
+                for (u32 c = tid; c < n_cls; c += nt) {
+                    u32 lo, hi;
+                    ooo_lanes(p, c, lo, hi);
+                    u64 rw = rot;
+                    bool tail = b0 && (summ >> w0 & 1ull);
+                    while (rw || tail) {
+                        u32 w;
+                        u64 bits;
+                        if (rw) {
+                            const u32 i = (u32)__builtin_ctzll(rw);
+                            rw &= rw - 1;
+                            w = (w0 + i) & (OOO_WORDS - 1);
+                            bits = tk[w];
+                            if (i == 0) bits &= ~0ull << b0;
+                        } else {
+                            tail = false;
+                            w = w0;
+                            bits = tk[w] & ((1ull << b0) - 1);
+                        }
                         while (bits) {
                             const u32 b = (u32)__builtin_ctzll(bits);
                             bits &= bits - 1;
                             const u32 s = w * 64 + b;
+                            const u32 ec = sh.e_cls[s];
+                            if ((ec & 0x7FFu) != c) continue;
+                            // independent loads first, so that their latencies overlap
+                            const u64 dur = sh.e_dur[s];
+                            const u32 eo0 = sh.e_o0[s], edeg = sh.e_deg[s];
                             const u32 y = first0 + ((s - fs) & (OOO_WR - 1));
-                            const u32 cls = sh.e_cls[s];
-                            const u32 lo = cls & 0xFFFFu, hi = cls >> 16;
+                            const u32 el = ec >> OOO_LANE_SHIFT;
                             ig_ooo_slot o;
                             o.issue = t;
                             if (lo == hi) {
@@ -292,38 +432,77 @@ IGD void ooo_engine(const OooGraph& g, const ig_ooo_params& p, OooShared& sh) {
                                 o.start = o.end = t;
                             } else {
                                 u32 L;
-                                if (sh.e_lane[s]) {
-                                    L = sh.e_lane[s] - 1u;
+                                if (el) {
+                                    L = el - 1u;
                                     o.how = IG_OOO_EAGER;
                                     ++n_eager;
                                 } else {
+                                    // the lane that frees up first, the lowest on ties
                                     L = lo;
-                                    for (u32 q = lo + 1; q < hi; ++q)
-                                        if (sh.busy[q] < sh.busy[L]) L = q;
+                                    u64 bl = OOO_INF;
+                                    for (u32 q0 = lo; q0 < hi; q0 += 4) {
+                                        u64 bq[4];
+#pragma unroll
+                                        for (u32 j = 0; j < 4; ++j) bq[j] = q0 + j < hi ? sh.lane[q0 + j].busy : OOO_INF;
+#pragma unroll
+                                        for (u32 j = 0; j < 4; ++j)
+                                            if (bq[j] < bl) {
+                                                bl = bq[j];
+                                                L = q0 + j;
+                                            }
+                                    }
                                     o.how = IG_OOO_DIRECT;
                                     ++direct;
                                 }
+                                OooLane ln = sh.lane[L];
                                 o.lane = L;
-                                o.start = t > sh.busy[L] ? t : sh.busy[L];
-                                o.end = o.start + sh.e_dur[s];
-                                sh.busy[L] = o.end;
-                                if (sh.head[L] == NONE) {
-                                    sh.head[L] = y;
-                                    sh.head_end[L] = o.end;
+                                o.start = t > ln.busy ? t : ln.busy;
+                                o.end = o.start + dur;
+                                ln.busy = o.end;
+                                if (ln.head == NONE) {
+                                    ln.head = y;
+                                    ln.head_end = o.end;
                                 } else {
-                                    g.next[sh.tail[L]] = y;
+                                    gmem(g.rec)[ln.tail].next = y;
+                                    gmem(g.rec)[ln.tail].next_end = o.end;
                                 }
-                                sh.tail[L] = y;
-                                g.next[y] = NONE;
+                                ln.tail = y;
+                                sh.lane[L] = ln;
+                                OooRec r;
+                                r.next = NONE;
+                                r.o0 = eo0;
+                                r.deg = edeg;
+                                r.pad = 0;
+                                r.next_end = OOO_INF;
+                                ooo_put_rec(g.rec + y, r);
                             }
                             makespan = o.end > makespan ? o.end : makespan;
-                            g.out[y] = o;
-                            sh.asg[s >> 6] |= 1ull << (s & 63);
-                            sh.done[nd++] = y;
+                            ooo_put_slot(g.out + y, o);
+                            const u64 at = atomicAdd(&sh.cnt[cur], 1ull << 32 | edeg);
+                            sh.d_o0[at >> 32] = eo0;
+                            sh.d_pre[at >> 32] = (u32)at;
                         }
                     }
+                }
+                if (tid == 0) {
+                    // beside the classes: clear the other parity's round
+                    // set, mark this round assigned, advance `first`
+                    u64 old = sh.take_sum[nxt];
+                    while (old) {
+                        const u32 w = (u32)__builtin_ctzll(old);
+                        old &= old - 1;
+                        sh.take[nxt][w] = 0;
+                    }
+                    sh.take_sum[nxt] = 0;
+                    sh.tmin[nxt] = OOO_INF;
+                    sh.cnt[nxt] = 0;
+                    u64 sw = summ;
+                    while (sw) {
+                        const u32 w = (u32)__builtin_ctzll(sw);
+                        sw &= sw - 1;
+                        sh.asg[w] |= tk[w];
+                    }
                     ++rounds;
-                    // advance the first unassigned id over the assigned run
                     u32 f = first0;
                     while (f < n) {
                         const u32 s = f & (OOO_WR - 1), w = s >> 6, b = s & 63;
@@ -337,29 +516,38 @@ IGD void ooo_engine(const OooGraph& g, const ig_ooo_params& p, OooShared& sh) {
                         f += adv;
                         if (adv < 64 - b) break;
                     }
-                    sh.first = f;
+                    sh.firstp[nxt] = f;
                     const u64 lo_w = (u64)first0 + W, hi_w = (u64)f + W;
                     sh.win_lo = lo_w < n ? (u32)lo_w : n;
                     sh.win_hi = hi_w < n ? (u32)hi_w : n;
-                    sh.n_done = nd;
                 }
                 ig_barrier_at(__LINE__);
-                ooo_propagate(g, sh, eager, W, next_sum);
+                OOO_PROF_MARK(1);
+                ooo_propagate(g, sh, p, sh.cnt[cur], sh.firstp[nxt], sh.take[nxt], &sh.take_sum[nxt]);
                 ig_barrier_at(__LINE__);
+                OOO_PROF_MARK(2);
             } else {
-                if (sh.first >= n) break;
+                if (first0 >= n) break;
+                OOO_PROF_MARK(3);
                 // the next completion: the earliest lane head
                 u64 m = OOO_INF;
-                for (u32 l = tid; l < n_lanes; l += nt) m = sh.head_end[l] < m ? sh.head_end[l] : m;
-                if (m != OOO_INF) atomicMin(&sh.tmin[it & 1], m);
+                for (u32 l = tid; l < n_lanes; l += nt) m = sh.lane[l].head_end < m ? sh.lane[l].head_end : m;
+                if (m != OOO_INF) atomicMin(&sh.tmin[cur], m);
                 if (tid == 0) {
-                    *next_sum = 0;
-                    sh.tmin[(it + 1) & 1] = OOO_INF;
-                    sh.n_done = 0;
+                    u64 old = sh.take_sum[nxt];
+                    while (old) {
+                        const u32 w = (u32)__builtin_ctzll(old);
+                        old &= old - 1;
+                        sh.take[nxt][w] = 0;
+                    }
+                    sh.take_sum[nxt] = 0;
+                    sh.tmin[nxt] = OOO_INF;
+                    sh.cnt[nxt] = 0;
+                    sh.firstp[nxt] = first0;
                     sh.win_lo = sh.win_hi = 0;
                 }
                 ig_barrier_at(__LINE__);
-                const u64 t = sh.tmin[it & 1];
+                const u64 t = sh.tmin[cur];
                 if (t == OOO_INF) {  // nothing in flight and nothing assignable
                     stalled = true;
                     break;
@@ -368,34 +556,46 @@ IGD void ooo_engine(const OooGraph& g, const ig_ooo_params& p, OooShared& sh) {
                     sh.t = t;
                     ++steps;
                 }
+                // each lane completes at most its head (ends strictly
+                // increase along a lane); one 64-bit counter hands out the
+                // entry index and the successor-list position together
                 for (u32 l = tid; l < n_lanes; l += nt) {
-                    if (sh.head_end[l] != t) continue;
-                    const u32 x = sh.head[l];
-                    if (x == sh.tail[l]) {
-                        sh.head[l] = NONE;
-                        sh.head_end[l] = OOO_INF;
+                    if (sh.lane[l].head_end != t) continue;
+                    const u32 x = sh.lane[l].head;
+                    const OooRec r = ooo_get_rec(g.rec + x);
+                    if (x == sh.lane[l].tail) {
+                        sh.lane[l].head = NONE;
+                        sh.lane[l].head_end = OOO_INF;
                     } else {
-                        const u32 nx = g.next[x];
-                        sh.head[l] = nx;
-                        sh.head_end[l] = g.out[nx].end;
+                        sh.lane[l].head = r.next;
+                        sh.lane[l].head_end = r.next_end;
                     }
-                    sh.done[atomicAdd(&sh.n_done, 1u)] = x;
+                    const u64 at = atomicAdd(&sh.cnt[cur], 1ull << 32 | r.deg);
+                    sh.d_o0[at >> 32] = r.o0;
+                    sh.d_pre[at >> 32] = (u32)at;
                 }
                 ig_barrier_at(__LINE__);
-                ooo_propagate(g, sh, eager, W, next_sum);
+                OOO_PROF_MARK(4);
+                ooo_propagate(g, sh, p, sh.cnt[cur], first0, sh.take[nxt], &sh.take_sum[nxt]);
                 ig_barrier_at(__LINE__);
+                OOO_PROF_MARK(5);
             }
         }
     }
+    if (direct) atomicAdd(&sh.r_direct, direct);
+    if (n_eager) atomicAdd(&sh.r_eager, n_eager);
+    if (makespan) atomicMax(&sh.r_makespan, makespan);
+    ig_barrier_at(__LINE__);
     if (tid == 0) {
         if (stalled) ooo_set_status(g, IG_E_INTERNAL);
         ig_ooo_summary s;
-        s.makespan = makespan;
-        s.direct = direct;
-        s.eager = n_eager;
+        s.makespan = sh.r_makespan;
+        s.direct = sh.r_direct;
+        s.eager = sh.r_eager;
         s.steps = steps;
         s.rounds = rounds;
         *g.sum = s;
+        OOO_PROF_REPORT;
     }
 }
 
@@ -404,30 +604,36 @@ IGD void ooo_engine(const OooGraph& g, const ig_ooo_params& p, OooShared& sh) {
 #ifndef IG_HOST_SIM
 using namespace igd;
 
+// Each kernel copies its graph descriptor (and the parameters) into
+// registers first: read through a pointer, the compiler would reload the
+// fields after every store it cannot prove does not alias them.
 __global__ void __launch_bounds__(256) ig_ooo_prep_nodes(const OooGraph* gs, ig_ooo_params p) {
-    const OooGraph& g = gs[blockIdx.y];
+    const OooGraph g = gs[blockIdx.y];
     if (blockIdx.x == 0 && threadIdx.x == 0) ooo_prep_tail(g);
     for (u32 x = blockIdx.x * blockDim.x + threadIdx.x; x < g.n; x += gridDim.x * blockDim.x) ooo_prep_node(g, p, x);
 }
 
 __global__ void __launch_bounds__(256) ig_ooo_prep_edges(const OooGraph* gs) {
-    const OooGraph& g = gs[blockIdx.y];
+    const OooGraph g = gs[blockIdx.y];
     for (u32 e = blockIdx.x * blockDim.x + threadIdx.x; e < g.ne; e += gridDim.x * blockDim.x) ooo_prep_edge(g, e);
 }
 
 __global__ void __launch_bounds__(256) ig_ooo_scan(const OooGraph* gs) {
     __shared__ u32 part[256];
-    ooo_scan(gs[blockIdx.x], part);
+    const OooGraph g = gs[blockIdx.x];
+    ooo_scan(g, part);
 }
 
 __global__ void __launch_bounds__(256) ig_ooo_fill(const OooGraph* gs) {
-    const OooGraph& g = gs[blockIdx.y];
+    const OooGraph g = gs[blockIdx.y];
     for (u32 e = blockIdx.x * blockDim.x + threadIdx.x; e < g.ne; e += gridDim.x * blockDim.x) ooo_fill_edge(g, e);
 }
 
 __global__ void __launch_bounds__(256) ig_ooo_engine(const OooGraph* gs, ig_ooo_params p) {
     __shared__ OooShared sh;
-    ooo_engine(gs[blockIdx.x], p, sh);
+    const OooGraph g = gs[blockIdx.x];
+    const ig_ooo_params pp = p;
+    ooo_engine(g, pp, sh);
 }
 
 namespace igrt {
