@@ -140,6 +140,17 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
 }
 #endif
 
+// Global-memory pointers in the kernels' device code: descriptors hold their
+// arrays as global-address-space pointers, so that accesses compile to
+// global (not flat) instructions, which do not count against the LDS wait
+// counter.  Host code (and translation units without kernels, which set no
+// IG_KERNEL_TU) sees plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__) && defined(IG_KERNEL_TU)
+#define IG_G __attribute__((address_space(1)))
+#else
+#define IG_G
+#endif
+
 namespace igd {
 
 typedef uint8_t u8;
@@ -279,84 +290,84 @@ struct DevCtx {
     u32 cmd_end;  // commands recorded (set by the host before a launch)
     u32 pad1;
     // --- command log ---
-    DevCmd* cmds;
+    IG_G DevCmd* cmds;
     // --- outputs (structure of arrays) ---
-    u8* i_kind;
-    u8* i_flags;
-    u16* i_mem;
-    u16* i_src_mem;
-    u32* i_task;
-    u32* i_chunk;
-    u32* i_buffer;
-    u32* i_alloc;
-    u32* i_src_alloc;
-    i64* i_box;  // [6][cap_instr]: min0 min1 min2 max0 max1 max2
-    u32* e_from;
-    u32* e_to;
-    u8* e_kinds;
-    u32* b_instr;
-    u32* b_access;
-    u32* b_alloc;
-    u8* has_succ;
-    i32* task_status;
-    u64* task_t0;   // [cap_cmds] device clock when the task's intake began
-    u64* task_tq;   // [cap_cmds] device clock when its intake ended (compiled at once or queued)
-    u64* task_tc;   // [cap_cmds] device clock when its compilation began
-    u64* task_t1;   // [cap_cmds] device clock when its records were complete
-    u64* phase;     // [32] device-clock ticks per analysis phase (profiling builds only)
+    IG_G u8* i_kind;
+    IG_G u8* i_flags;
+    IG_G u16* i_mem;
+    IG_G u16* i_src_mem;
+    IG_G u32* i_task;
+    IG_G u32* i_chunk;
+    IG_G u32* i_buffer;
+    IG_G u32* i_alloc;
+    IG_G u32* i_src_alloc;
+    IG_G i64* i_box;  // [6][cap_instr]: min0 min1 min2 max0 max1 max2
+    IG_G u32* e_from;
+    IG_G u32* e_to;
+    IG_G u8* e_kinds;
+    IG_G u32* b_instr;
+    IG_G u32* b_access;
+    IG_G u32* b_alloc;
+    IG_G u8* has_succ;
+    IG_G i32* task_status;
+    IG_G u64* task_t0;   // [cap_cmds] device clock when the task's intake began
+    IG_G u64* task_tq;   // [cap_cmds] device clock when its intake ended (compiled at once or queued)
+    IG_G u64* task_tc;   // [cap_cmds] device clock when its compilation began
+    IG_G u64* task_t1;   // [cap_cmds] device clock when its records were complete
+    IG_G u64* phase;     // [32] device-clock ticks per analysis phase (profiling builds only)
     // --- state ---
-    DBuf* bufs;       // [MAX_BUF]
-    DAlloc* allocs;   // [cap_allocs]
-    u32* live_n;      // [MAX_BUF * n_mem]
-    u32* live;        // [MAX_BUF * n_mem * MAX_LIVE]
-    u32* plan_n;      // [MAX_BUF * n_mem]  NONE: not planned (use live)
-    i64* plan;        // [MAX_BUF * n_mem * MAX_PLAN * 6]
-    u32* queue;       // [cap_queue] command index, top bit: horizon
-    u32* heap;        // [cap_heap] words
-    u32* heap_free;   // [32] free-list heads per size class
-    u32* rb;          // [cap_rb * 8] reader blocks
-    u64* rb_free;         // [n_mem] free reader blocks per memory: tag << 32 | head
+    IG_G DBuf* bufs;       // [MAX_BUF]
+    IG_G DAlloc* allocs;   // [cap_allocs]
+    IG_G u32* live_n;      // [MAX_BUF * n_mem]
+    IG_G u32* live;        // [MAX_BUF * n_mem * MAX_LIVE]
+    IG_G u32* plan_n;      // [MAX_BUF * n_mem]  NONE: not planned (use live)
+    IG_G i64* plan;        // [MAX_BUF * n_mem * MAX_PLAN * 6]
+    IG_G u32* queue;       // [cap_queue] command index, top bit: horizon
+    IG_G u32* heap;        // [cap_heap] words
+    IG_G u32* heap_free;   // [32] free-list heads per size class
+    IG_G u32* rb;          // [cap_rb * 8] reader blocks
+    IG_G u64* rb_free;         // [n_mem] free reader blocks per memory: tag << 32 | head
     // --- per-command scratch ---
-    Region* reg;          // [MAX_CHUNKS * IG_MAX_ACCESS]
-    i64* chunk_lo;        // [MAX_CHUNKS]
-    i64* chunk_hi;        // [MAX_CHUNKS]
-    u32* cons_off;        // [MAX_CHUNKS * IG_MAX_ACCESS]
-    u32* cons_cnt;        // [MAX_CHUNKS * IG_MAX_ACCESS]
-    u32* cons_x;          // [MAX_CHUNKS * IG_MAX_ACCESS] first copy of (chunk, access) within its device
-    u32* k_rank;          // [MAX_CHUNKS] kernel index of a chunk within its device (NONE: empty)
-    u32* big_n;           // [n_mem] large coherence reads deferred to the team scan
-    u32* big_idx;         // [n_mem * MAX_BIG] their (chunk * IG_MAX_ACCESS + access)
-    u32* tm;              // [n_mem * 4] words a thread team shares (offsets, totals, flags)
-    CopyRec* copies;      // [cap_unit]
-    u32* dev_cnt;         // [n_dev] copies per device, then kernels per device
-    u32* dev_base;        // [n_dev]
-    u32* kdev_cnt;        // [n_dev]
-    u32* kdev_base;       // [n_dev]
-    u32* inbox_cnt;       // [n_mem]
-    u32* inbox_off;       // [n_mem]
-    u32* inbox_cur;       // [n_mem]
-    InboxRec* inbox;      // [cap_unit]
-    u32* tab_off;         // [cap_unit] staged edges of each instruction of the unit
-    u32* tab_cnt;         // [cap_unit]
-    u32* stage_from;      // [cap_unit * 4]
-    u8* stage_kind;       // [cap_unit * 4]
-    u32* pair_flag;       // [MAX_BUF * n_mem] (allocation phase)
-    u32* pair_cnt;        // [MAX_BUF * n_mem]
-    u32* pair_acnt;       // [MAX_BUF * n_mem]
-    u32* miss_n;          // [1]
-    i64* miss_val;        // [cap_scr]
-    u32* miss_bd;         // [cap_scr] buffer*4+dim
-    u32* remap;           // [3 * cap_scr] old cell of new cell, per dim
+    IG_G Region* reg;          // [MAX_CHUNKS * IG_MAX_ACCESS]
+    IG_G i64* chunk_lo;        // [MAX_CHUNKS]
+    IG_G i64* chunk_hi;        // [MAX_CHUNKS]
+    IG_G u32* cons_off;        // [MAX_CHUNKS * IG_MAX_ACCESS]
+    IG_G u32* cons_cnt;        // [MAX_CHUNKS * IG_MAX_ACCESS]
+    IG_G u32* cons_x;          // [MAX_CHUNKS * IG_MAX_ACCESS] first copy of (chunk, access) within its device
+    IG_G u32* k_rank;          // [MAX_CHUNKS] kernel index of a chunk within its device (NONE: empty)
+    IG_G u32* big_n;           // [n_mem] large coherence reads deferred to the team scan
+    IG_G u32* big_idx;         // [n_mem * MAX_BIG] their (chunk * IG_MAX_ACCESS + access)
+    IG_G u32* tm;              // [n_mem * 4] words a thread team shares (offsets, totals, flags)
+    IG_G CopyRec* copies;      // [cap_unit]
+    IG_G u32* dev_cnt;         // [n_dev] copies per device, then kernels per device
+    IG_G u32* dev_base;        // [n_dev]
+    IG_G u32* kdev_cnt;        // [n_dev]
+    IG_G u32* kdev_base;       // [n_dev]
+    IG_G u32* inbox_cnt;       // [n_mem]
+    IG_G u32* inbox_off;       // [n_mem]
+    IG_G u32* inbox_cur;       // [n_mem]
+    IG_G InboxRec* inbox;      // [cap_unit]
+    IG_G u32* tab_off;         // [cap_unit] staged edges of each instruction of the unit
+    IG_G u32* tab_cnt;         // [cap_unit]
+    IG_G u32* stage_from;      // [cap_unit * 4]
+    IG_G u8* stage_kind;       // [cap_unit * 4]
+    IG_G u32* pair_flag;       // [MAX_BUF * n_mem] (allocation phase)
+    IG_G u32* pair_cnt;        // [MAX_BUF * n_mem]
+    IG_G u32* pair_acnt;       // [MAX_BUF * n_mem]
+    IG_G u32* miss_n;          // [1]
+    IG_G i64* miss_val;        // [cap_scr]
+    IG_G u32* miss_bd;         // [cap_scr] buffer*4+dim
+    IG_G u32* remap;           // [3 * cap_scr] old cell of new cell, per dim
     // --- per-worker scratch ---
-    u64* wk_key;   // [n_workers * cap_scr]
-    u32* wk_val;   // [n_workers * cap_scr]
-    u64* wk_key2;  // [n_workers * cap_scr]
-    u32* wk_val2;  // [n_workers * cap_scr]
-    u64* wk_rsrc;  // [n_workers * RD_CACHE * cap_src] sources of shared read scans
-    RdGroup* wk_grp;  // [n_workers * RD_CACHE] read groups
-    u64* wk_src;   // [threads * cap_src]
-    u64* wk_src2;  // [threads * cap_src]
-    i64* wk_box;   // [n_workers * cap_box * 6]
+    IG_G u64* wk_key;   // [n_workers * cap_scr]
+    IG_G u32* wk_val;   // [n_workers * cap_scr]
+    IG_G u64* wk_key2;  // [n_workers * cap_scr]
+    IG_G u32* wk_val2;  // [n_workers * cap_scr]
+    IG_G u64* wk_rsrc;  // [n_workers * RD_CACHE * cap_src] sources of shared read scans
+    IG_G RdGroup* wk_grp;  // [n_workers * RD_CACHE] read groups
+    IG_G u64* wk_src;   // [threads * cap_src]
+    IG_G u64* wk_src2;  // [threads * cap_src]
+    IG_G i64* wk_box;   // [n_workers * cap_box * 6]
     // --- persistent scalars ---
     Scalars s;
 };

@@ -19,6 +19,7 @@
 // Sec. 4.3 (lookahead), Sec. 4.4 (debug checks).
 #include <mutex>
 
+#define IG_KERNEL_TU 1
 #include "ig_dev.h"
 
 namespace igd {

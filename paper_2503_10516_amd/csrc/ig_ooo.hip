@@ -22,6 +22,7 @@
 //     the workspace); with positive durations their ends strictly increase
 //     along a lane, so the next completion is the minimum over lane heads
 //     and at most one instruction per lane completes at a moment.
+#define IG_KERNEL_TU 1
 #include "ig_dev.h"
 
 // Per-phase clock totals of the engine's first thread, printed at the end
