@@ -294,6 +294,12 @@ def run_batched(args, copy_gbs):
                             "analysis_ms": float(times[heavy][:, 3].max() / 1e6)},
     }
     out.update(lat)
+    if "ooo" in set(args.workloads.split(",")):
+        out["ooo"] = ooo_run(bt.contexts, max(x.nodes * x.devices for x in ss), max(args.steps, 3), copy_gbs)
+        out["ooo"]["workload"] = ("engine over the 256 batched graphs, one workgroup each, one launch: 2 lanes "
+                                  "per device, 2 host lanes, window 1024, eager assignment")
+        log(f"ooo batched: {out['ooo']['instructions_per_s']:.3g} instructions/s, "
+            f"{np.median(out['ooo']['run_ms']):.1f} ms")
     bt.close()
     return records, out, gold
 
@@ -386,6 +392,78 @@ def run_task_graph_horizons(threads):
     return out
 
 
+# ---------------------------------------------------------------------------
+# Out-of-order engine simulation (Sec. 4.1) over finished graphs
+# ---------------------------------------------------------------------------
+
+def ooo_algorithmic_bytes(n_instr, n_edges):
+    """Bytes the engine must move at least: per instruction its result slot
+    (32 written), its in-flight record (24 written), its lane class,
+    duration and the two offset pairs (28 read); per edge the successor entry
+    (12), the dependency id (4) and the dependency's end and lane (12)."""
+    return 84 * n_instr + 28 * n_edges
+
+
+def ooo_run(contexts, devices, steps, copy_gbs):
+    """Time `steps` runs of the engine over the contexts' graphs (one launch
+    of the preparation kernels and the engine, HIP events on the stream)."""
+    import numpy as np
+    import torch
+    from paper_2503_10516_amd import binding
+    p = binding.ooo_params(devices)
+    sim = binding.OooSimulation(contexts, p)
+    stream = torch.cuda.current_stream()
+    sim.run(stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        sim.run(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in ev]
+    summ = [sim.summary(i) for i in range(len(contexts))]
+    sim.close()
+    n = sum(int(c.counts()[0]) for c in contexts)
+    ne = sum(int(c.counts()[2]) for c in contexts)
+    sec = float(np.median(ms)) / 1e3
+    ab = ooo_algorithmic_bytes(n, ne)
+    return {"graphs": len(contexts), "instructions": n, "edges": ne, "run_ms": ms,
+            "instructions_per_s": n / sec, "summaries": summ if len(summ) == 1 else None,
+            "makespan_ns_max": max(s["makespan"] for s in summ),
+            "eager_fraction": sum(s["eager"] for s in summ) / max(1, n),
+            "roofline": {"bound": "hbm", "achieved": ab / sec / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": ab / sec / 1e9 / PEAK_HBM_GBS, "traffic": None,
+                         "kernel": "ig_ooo_prep_* + ig_ooo_engine", "algorithmic_bytes": ab,
+                         "frac_of_copy": ab / sec / 1e9 / copy_gbs if copy_gbs else None}}
+
+
+def run_ooo_stencil2d(steps, threads, copy_gbs):
+    """The engine over the 2-D stencil's graph (one workgroup), compared
+    with the oracle's engine stored in tests/golden."""
+    import numpy as np
+    from paper_2503_10516_amd import binding, streams
+    s = streams.stencil_2d()
+    ctx = binding.make_context(s, threads=threads)
+    ctx.record(s)
+    ctx.flush()
+    assert ctx.sync() == 0
+    out = ooo_run([ctx], s.nodes * s.devices, steps, copy_gbs)
+    gold = load_json(os.path.join(GOLDEN, "stencil2d_full_ooo.json"))
+    if gold:
+        sim = binding.OooSimulation([ctx], binding.ooo_params(s.nodes * s.devices))
+        sim.run()
+        slots, summ = sim.fetch(0)
+        sim.close()
+        import hashlib
+        out["oracle_equal"] = summ == gold["summary"] and \
+            hashlib.sha256(slots.tobytes()).hexdigest() == gold["slots_sha256"]
+    ctx.close()
+    out["workload"] = ("engine over the 2-D stencil's graph (16 nodes x 8 devices, 1000 tasks): 2 lanes per "
+                       "device, 2 host lanes, window 1024, eager assignment, cost model of binding.ooo_params")
+    return out
+
+
 def run_serving(args):
     from paper_2503_10516_amd import serve, streams
     sessions = streams.serving_sessions(n_sessions=args.serving_sessions)
@@ -415,9 +493,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--threads", type=int, default=256, help="workgroup size of the single-stream objects")
-    ap.add_argument("--workloads", default="stencil2d,nbody,stencil1d,tdag,serving",
+    ap.add_argument("--workloads", default="stencil2d,nbody,stencil1d,tdag,serving,ooo",
                     help="comma list of objects beside the batched headline: stencil2d, nbody, stencil1d, tdag "
-                         "(horizons from the task graph), serving")
+                         "(horizons from the task graph), serving, ooo (the out-of-order engine simulated over "
+                         "the 2-D stencil's and the batched graphs)")
     ap.add_argument("--batch-threads", type=int, default=0, help="0: autotune")
     ap.add_argument("--batch-window", type=int, default=400, help="commands per launch while sizing")
     ap.add_argument("--serving-rates", default="1e3,1e5")
@@ -501,6 +580,10 @@ def main():
         line["task_graph_horizons"] = run_task_graph_horizons(args.threads)
     if "serving" in work:
         line["serving"] = run_serving(args)
+    if "ooo" in work:
+        line["ooo"] = {"stencil2d": run_ooo_stencil2d(max(args.steps, 3), args.threads, copy_gbs),
+                       "batched": line["batched"].pop("ooo", None)}
+        log(f"ooo stencil2d: {line['ooo']['stencil2d']['instructions_per_s']:.3g} instructions/s")
     print(json.dumps(line))
 
 

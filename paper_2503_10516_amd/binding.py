@@ -726,6 +726,15 @@ class OooSimulation:
             raise IgError("ig_ooo_slots", st)
         return ptr.value, n.value
 
+    def summary(self, i: int) -> Dict[str, int]:
+        """Graph i's summary alone (waits for the last run)."""
+        summ = OooSummary()
+        got = ctypes.c_size_t()
+        st = self.L.ig_ooo_fetch(self.h, i, None, 0, ctypes.byref(got), ctypes.byref(summ))
+        if st != 0:
+            raise IgError(f"ig_ooo_fetch (graph {i})", st)
+        return {k: getattr(summ, k) for k, _ in OooSummary._fields_}
+
     def fetch(self, i: int):
         """(slots as OOO_SLOT_DTYPE, summary dict) of graph i."""
         _, n = self.device_slots(i)

@@ -133,7 +133,17 @@ template <class T>
 inline T* gmem(T* p) {
     return p;
 }
+template <class T>
+inline T ig_load_agent(const T* p) {
+    return __atomic_load_n(p, __ATOMIC_SEQ_CST);
+}
 #else
+// A load that reads the level-2 cache, where atomics are performed, not a
+// possibly older copy in the compute unit's level-1 cache.
+template <class T>
+__device__ __forceinline__ T ig_load_agent(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 template <class T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
     return (__attribute__((address_space(1))) T*)p;
@@ -379,9 +389,14 @@ struct DevStats {
     unsigned long long per_dep[5];
 };
 
-// A successor y with its dependency list [k0, k1) (edges sorted by target).
-struct OooSucc {
-    u32 y, k0, k1;
+// What the engine knows of an instruction's dependencies, kept current as
+// they are assigned and complete: how many are not yet assigned, how many
+// are incomplete on lanes outside its class, and of those incomplete on its
+// class's lanes the count, the sum of their lanes and of the squares (all on
+// one lane exactly when count * squares == sum^2).
+struct OooCnt {
+    u32 unasg, foreign, inc, suml;
+    u64 sumsq;
 };
 // Per instruction while it is in flight: the next instruction on its lane
 // and that one's end, and its own successor list (offset, length).
@@ -408,7 +423,8 @@ struct OooGraph {
     // workspace
     u32* in_off;   // [n + 1] first edge of each target
     u32* out_off;  // [n + 1] successor list offsets (counts before the scan)
-    OooSucc* out_adj;  // [ne] successors with their dependency-list ranges
+    u32* out_adj;  // [ne] successors
+    OooCnt* cnt;   // [n] dependency state
     OooRec* rec;   // [n] lane FIFO links and successor ranges (fill cursors during preparation)
     u32* cls;      // [n] lane class
     u64* dur;      // [n]

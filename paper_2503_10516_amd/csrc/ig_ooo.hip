@@ -62,7 +62,6 @@ struct OooLane {
     u64 busy;
     u64 head_end;
     u32 head, tail;
-    u64 pad;
 };
 
 struct OooShared {
@@ -80,6 +79,7 @@ struct OooShared {
     // list offset and position in the concatenation of the lists
     u32 d_o0[OOO_WR];
     u32 d_pre[OOO_WR];
+    u32 d_lane[OOO_WR];
     // by loop-iteration parity (one is read while the other is prepared):
     u64 take_sum[2];   // non-empty words of take[]
     u64 tmin[2];       // the next completion
@@ -99,20 +99,6 @@ IGD void ooo_put_slot(ig_ooo_slot* p, const ig_ooo_slot& o) {
     q->issue = o.issue;
     q->start = o.start;
     q->end = o.end;
-}
-IGD void ooo_put_succ(OooSucc* p, const OooSucc& v) {
-    auto q = gmem(p);
-    q->y = v.y;
-    q->k0 = v.k0;
-    q->k1 = v.k1;
-}
-IGD OooSucc ooo_get_succ(const OooSucc* p) {
-    auto q = gmem(p);
-    OooSucc v;
-    v.y = q->y;
-    v.k0 = q->k0;
-    v.k1 = q->k1;
-    return v;
 }
 IGD void ooo_put_rec(OooRec* p, const OooRec& v) {
     auto q = gmem(p);
@@ -185,7 +171,12 @@ IGD void ooo_prep_node(const OooGraph& g, const ig_ooo_params& p, u32 x) {
     }
     gmem(g.cls)[x] = cls;
     gmem(g.dur)[x] = dur;
-    gmem(g.in_off)[x] = ooo_lower_bound(g.e_to, g.ne, x);
+    const u32 k0 = ooo_lower_bound(g.e_to, g.ne, x), k1 = ooo_lower_bound(g.e_to, g.ne, x + 1);
+    gmem(g.in_off)[x] = k0;
+    auto c = gmem(g.cnt) + x;
+    c->unasg = k1 - k0;
+    c->foreign = c->inc = c->suml = 0;
+    c->sumsq = 0;
     gmem(g.out_off)[x] = 0;
     ig_ooo_slot s;
     s.lane = NONE;
@@ -250,12 +241,7 @@ IGD void ooo_scan(const OooGraph& g, u32* part) {
 IGD void ooo_fill_edge(const OooGraph& g, u32 e) {
     if (!ooo_edge_ok(g, e)) return;  // not counted either
     const u32 pos = atomicAdd(&g.rec[gmem(g.e_from)[e]].next, 1u);
-    const u32 y = gmem(g.e_to)[e];
-    OooSucc sc;
-    sc.y = y;
-    sc.k0 = gmem(g.in_off)[y];
-    sc.k1 = gmem(g.in_off)[y + 1];
-    ooo_put_succ(g.out_adj + pos, sc);
+    gmem(g.out_adj)[pos] = gmem(g.e_to)[e];
 }
 
 // The lanes [lo, hi) of a class (lo == hi: the engine's own).
@@ -272,42 +258,52 @@ IGD void ooo_lanes(const ig_ooo_params& p, u32 cls, u32& lo, u32& hi) {
     }
 }
 
-// Is y assignable at time t (all dependencies complete, or with eager all
-// incomplete ones on one lane of y's class)?  If so, mark it for the next
-// round (its non-empty word in *tsum) with what the assignment and the
-// following propagation need.  Called for any id; filters itself.  The
-// dependencies are read four at a time so that their loads overlap.
-IGD void ooo_eval(const OooGraph& g, OooShared& sh, const ig_ooo_params& p, u32 y, u32 k0, u32 k1, u64 t, u32 first,
-                  u32 win_end, u64* take, u64* tsum) {
+// A dependency of y changed: it was assigned (to `lane`, NONE for the
+// engine's own, which complete at once) or it completed on `lane`.
+IGD void ooo_update(const OooGraph& g, const ig_ooo_params& p, u32 y, u32 lane, bool completed) {
+    OooCnt* c = g.cnt + y;
+    if (!completed) atomicAdd(&c->unasg, 0xFFFFFFFFu);  // - 1
+    if (lane == NONE) return;
+    u32 lo, hi;
+    ooo_lanes(p, gmem(g.cls)[y], lo, hi);
+    const u32 d = completed ? 0xFFFFFFFFu : 1u;  // -1 or +1, modulo 2^32
+    if (lane < lo || lane >= hi) {
+        atomicAdd(&c->foreign, d);
+        return;
+    }
+    atomicAdd(&c->inc, d);
+    atomicAdd(&c->suml, completed ? 0u - lane : lane);
+    const u64 sq = (u64)lane * lane;
+    atomicAdd(&c->sumsq, completed ? 0ull - sq : sq);
+}
+
+// Is y assignable now (all dependencies complete, or with eager all
+// incomplete ones assigned to one lane of y's class)?  If so, mark it for
+// the next round with what the assignment and the following propagation
+// need.  Called for any id; filters itself.  The dependency state is read
+// from the level-2 cache (agent-scope loads), where the updates' atomics
+// were performed.
+IGD void ooo_eval(const OooGraph& g, OooShared& sh, const ig_ooo_params& p, u32 y, u32 first, u32 win_end, u64* take,
+                  u64* tsum) {
     if (y < first || y >= win_end) return;
     const u32 s = y & (OOO_WR - 1);
     if ((sh.asg[s >> 6] >> (s & 63)) & 1ull) return;
+    const OooCnt* c = g.cnt + y;
+    const u32 unasg = ig_load_agent(&c->unasg), foreign = ig_load_agent(&c->foreign);
+    const u32 inc = ig_load_agent(&c->inc), suml = ig_load_agent(&c->suml);
+    const u64 sumsq = ig_load_agent(&c->sumsq);
     const u32 cls = gmem(g.cls)[y];
     const u32 o0 = gmem(g.out_off)[y], o1 = gmem(g.out_off)[y + 1];
     const u64 dur = gmem(g.dur)[y];
-    u32 lo, hi;
-    ooo_lanes(p, cls, lo, hi);
-    const u32 eager = p.eager;
+    if (unasg || foreign) return;
     u32 L = NONE;
-    for (u32 k = k0; k < k1; k += 4) {
-        u32 d[4];
-#pragma unroll
-        for (u32 q = 0; q < 4; ++q) d[q] = k + q < k1 ? gmem(g.e_from)[k + q] : NONE;
-        u64 end[4];
-        u32 lane[4];
-#pragma unroll
-        for (u32 q = 0; q < 4; ++q) {
-            end[q] = d[q] != NONE ? gmem(g.out)[d[q]].end : 0ull;
-            lane[q] = d[q] != NONE ? gmem(g.out)[d[q]].lane : NONE;
-        }
-#pragma unroll
-        for (u32 q = 0; q < 4; ++q) {
-            if (end[q] <= t) continue;
-            // incomplete (or unassigned: lane NONE, end infinite)
-            if (!eager || lo == hi) return;
-            if (lane[q] < lo || lane[q] >= hi || (L != NONE && lane[q] != L)) return;
-            L = lane[q];
-        }
+    if (inc) {
+        u32 lo, hi;
+        ooo_lanes(p, cls, lo, hi);
+        if (!p.eager || lo == hi) return;
+        // all on one lane: inc * sum of squares == (sum)^2, in 128 bits
+        if ((unsigned __int128)inc * sumsq != (unsigned __int128)suml * suml) return;
+        L = suml / inc;
     }
     sh.e_cls[s] = cls | (L == NONE ? 0u : (L + 1) << OOO_LANE_SHIFT);
     sh.e_dur[s] = dur;
@@ -318,28 +314,38 @@ IGD void ooo_eval(const OooGraph& g, OooShared& sh, const ig_ooo_params& p, u32 
     if (!(old & bit)) atomicOr(tsum, 1ull << (s >> 6));
 }
 
-// Evaluate the successors of the changed instructions (cnt: entries << 32
-// | successors; entry i: successor list from d_o0[i], at position d_pre[i]
-// of the concatenation; one thread per successor) and the ids newly in the
-// window [win_lo, win_hi); marks go to take / tsum.
-IGD void ooo_propagate(const OooGraph& g, OooShared& sh, const ig_ooo_params& p, u64 cnt, u32 first, u64* take,
-                       u64* tsum) {
+// The entry of the changed list holding successor j of the concatenation.
+IGD u32 ooo_entry(const OooShared& sh, u32 nd, u32 j) {
+    u32 lo = 0, hi = nd;  // the last entry starting at or before j
+    while (hi - lo > 1) {
+        const u32 mid = (lo + hi) >> 1;
+        if (sh.d_pre[mid] <= j) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// The successors of the changed instructions (cnt: entries << 32 |
+// successors; entry i: successor list from d_o0[i], at position d_pre[i] of
+// the concatenation, lane d_lane[i]; one thread per successor): first their
+// dependency state is updated, then (after a barrier) they are evaluated,
+// with the ids newly in the window [win_lo, win_hi); marks go to take /
+// tsum.
+IGD void ooo_propagate(const OooGraph& g, OooShared& sh, const ig_ooo_params& p, u64 cnt, bool completed, u32 first,
+                       u64* take, u64* tsum) {
     const u32 tid = ig_tid(), nt = ig_nthreads();
-    const u64 t = sh.t;
     const u32 win_end = (u64)first + p.window < g.n ? first + p.window : g.n;
     const u32 nd = (u32)(cnt >> 32), total = (u32)cnt;
     for (u32 j = tid; j < total; j += nt) {
-        u32 lo = 0, hi = nd;  // the last entry starting at or before j
-        while (hi - lo > 1) {
-            const u32 mid = (lo + hi) >> 1;
-            if (sh.d_pre[mid] <= j) lo = mid;
-            else hi = mid;
-        }
-        const OooSucc sc = ooo_get_succ(g.out_adj + sh.d_o0[lo] + (j - sh.d_pre[lo]));
-        ooo_eval(g, sh, p, sc.y, sc.k0, sc.k1, t, first, win_end, take, tsum);
+        const u32 i = ooo_entry(sh, nd, j);
+        ooo_update(g, p, gmem(g.out_adj)[sh.d_o0[i] + (j - sh.d_pre[i])], sh.d_lane[i], completed);
     }
-    for (u32 y = sh.win_lo + tid; y < sh.win_hi; y += nt)
-        ooo_eval(g, sh, p, y, gmem(g.in_off)[y], gmem(g.in_off)[y + 1], t, first, win_end, take, tsum);
+    ig_barrier_at(__LINE__);
+    for (u32 j = tid; j < total; j += nt) {
+        const u32 i = ooo_entry(sh, nd, j);
+        ooo_eval(g, sh, p, gmem(g.out_adj)[sh.d_o0[i] + (j - sh.d_pre[i])], first, win_end, take, tsum);
+    }
+    for (u32 y = sh.win_lo + tid; y < sh.win_hi; y += nt) ooo_eval(g, sh, p, y, first, win_end, take, tsum);
 }
 
 // The engine, one workgroup per graph.
@@ -354,7 +360,6 @@ IGD void ooo_engine(const OooGraph& g, const ig_ooo_params& p, OooShared& sh) {
         z.busy = 0;
         z.head_end = OOO_INF;
         z.head = z.tail = NONE;
-        z.pad = 0;
         sh.lane[l] = z;
     }
     if (tid == 0) {
@@ -375,7 +380,7 @@ IGD void ooo_engine(const OooGraph& g, const ig_ooo_params& p, OooShared& sh) {
     bool stalled = false;
     OOO_PROF_DECL;
     if (!bad && n) {
-        ooo_propagate(g, sh, p, 0, 0, sh.take[0], &sh.take_sum[0]);
+        ooo_propagate(g, sh, p, 0, false, 0, sh.take[0], &sh.take_sum[0]);
         ig_barrier_at(__LINE__);
         // Iteration `it` reads the state of parity it & 1 and prepares that
         // of parity (it + 1) & 1, which nobody reads during the iteration.
@@ -482,6 +487,7 @@ IGD void ooo_engine(const OooGraph& g, const ig_ooo_params& p, OooShared& sh) {
                             const u64 at = atomicAdd(&sh.cnt[cur], 1ull << 32 | edeg);
                             sh.d_o0[at >> 32] = eo0;
                             sh.d_pre[at >> 32] = (u32)at;
+                            sh.d_lane[at >> 32] = o.lane;
                         }
                     }
                 }
@@ -524,7 +530,7 @@ IGD void ooo_engine(const OooGraph& g, const ig_ooo_params& p, OooShared& sh) {
                 }
                 ig_barrier_at(__LINE__);
                 OOO_PROF_MARK(1);
-                ooo_propagate(g, sh, p, sh.cnt[cur], sh.firstp[nxt], sh.take[nxt], &sh.take_sum[nxt]);
+                ooo_propagate(g, sh, p, sh.cnt[cur], false, sh.firstp[nxt], sh.take[nxt], &sh.take_sum[nxt]);
                 ig_barrier_at(__LINE__);
                 OOO_PROF_MARK(2);
             } else {
@@ -574,10 +580,11 @@ IGD void ooo_engine(const OooGraph& g, const ig_ooo_params& p, OooShared& sh) {
                     const u64 at = atomicAdd(&sh.cnt[cur], 1ull << 32 | r.deg);
                     sh.d_o0[at >> 32] = r.o0;
                     sh.d_pre[at >> 32] = (u32)at;
+                    sh.d_lane[at >> 32] = l;
                 }
                 ig_barrier_at(__LINE__);
                 OOO_PROF_MARK(4);
-                ooo_propagate(g, sh, p, sh.cnt[cur], first0, sh.take[nxt], &sh.take_sum[nxt]);
+                ooo_propagate(g, sh, p, sh.cnt[cur], true, first0, sh.take[nxt], &sh.take_sum[nxt]);
                 ig_barrier_at(__LINE__);
                 OOO_PROF_MARK(5);
             }

@@ -10,6 +10,7 @@ which the benchmark's roofline numerator uses.
     python tests/golden/make_golden.py nbody_full growing_q8 ...
     python tests/golden/make_golden.py batched 6      # the 256 batched streams, 6 processes
     python tests/golden/make_golden.py serving 3      # each kind of serving session
+    python tests/golden/make_golden.py ooo            # the engine simulation over the 2-D stencil's graph
 """
 import json
 import os
@@ -120,9 +121,40 @@ def serving(workers):
     print(sorted(rows))
 
 
+OOO_FILE = "stencil2d_full_ooo.json"
+OOO_CASES = [{}, {"window": 64, "eager": 0}]  # changes to the defaults of oracle.ooo_params
+
+
+def ooo():
+    """The oracle's out-of-order engine (Sec. 4.1) over the 2-D stencil's
+    graph: per parameter set the summary, a SHA-256 of every result slot and
+    the first and last slots."""
+    import hashlib
+    s = S.stencil_2d()
+    out = oracle.run_stream(s, fetch=True)
+    doc = {"case": "stencil2d_full", "devices": s.nodes * s.devices, "runs": []}
+    keep = {}
+    for j, kw in enumerate(OOO_CASES):
+        p = oracle.ooo_params(s.nodes * s.devices, **kw)
+        t = time.time()
+        slots, summ = oracle.ooo_simulate(out["instructions"], out["edges"], p)
+        doc["runs"].append({"params": kw, "summary": summ, "slots_sha256": hashlib.sha256(slots.tobytes()).hexdigest(),
+                            "oracle_seconds": round(time.time() - t, 1)})
+        keep[f"slots{j}"] = head_tail(slots, 1000)
+        print("ooo", kw, summ, flush=True)
+    # the default parameters also at the top level (read by the benchmark)
+    doc["summary"] = doc["runs"][0]["summary"]
+    doc["slots_sha256"] = doc["runs"][0]["slots_sha256"]
+    with open(os.path.join(HERE, OOO_FILE), "w") as f:
+        json.dump(doc, f, indent=1)
+    np.savez_compressed(os.path.join(HERE, "stencil2d_full_ooo_slots.npz"), **keep)
+
+
 if __name__ == "__main__":
     if sys.argv[1:2] == ["serving"]:
         serving(int(sys.argv[2]) if len(sys.argv) > 2 else 3)
+    elif sys.argv[1:2] == ["ooo"]:
+        ooo()
     elif sys.argv[1:2] == ["batched"]:
         batched(int(sys.argv[2]) if len(sys.argv) > 2 else 4)
     else:

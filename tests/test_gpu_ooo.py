@@ -4,6 +4,10 @@ and the summary, bit for bit, over graphs the HIP path generated (which
 equal the oracle's, checked elsewhere).  At full size, where the oracle's
 engine would take hours, the properties that hold for any correct run are
 checked instead."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -140,5 +144,30 @@ def test_ooo_full_size_stencil2d_properties():
             sim.close()
             check_engine_properties(out["instructions"], out["edges"], slots, summ, p, s.nodes * s.devices *
                                     p.lanes_per_device)
+    finally:
+        ctx.close()
+
+
+def test_ooo_full_size_stencil2d_against_oracle_golden():
+    """Every slot of the engine over the full 2-D stencil's graph equals the
+    oracle's (stored by tests/golden/make_golden.py: SHA-256 of all slots,
+    the first and last 1000 verbatim, the summary), for two parameter sets."""
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    gold = json.load(open(os.path.join(here, "stencil2d_full_ooo.json")))
+    keep = np.load(os.path.join(here, "stencil2d_full_ooo_slots.npz"))
+    s = S.stencil_2d()
+    print("[gpu] ooo stencil2d full against the oracle golden", flush=True)
+    ctx = _contexts([s])[0]
+    try:
+        for j, run in enumerate(gold["runs"]):
+            sim = B.OooSimulation([ctx], B.ooo_params(gold["devices"], **run["params"]))
+            sim.run()
+            slots, summ = sim.fetch(0)
+            sim.close()
+            assert summ == run["summary"], (run["params"], summ)
+            want = keep[f"slots{j}"]
+            got = np.concatenate([slots[:1000], slots[-1000:]])
+            assert got.tobytes() == want.tobytes(), run["params"]
+            assert hashlib.sha256(slots.tobytes()).hexdigest() == run["slots_sha256"], run["params"]
     finally:
         ctx.close()
