@@ -63,16 +63,17 @@ def algorithmic_bytes(t):
             + 88 * t["u_b"] + 48 * t["map_boxes"])
 
 
-def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
+def kernel_sha(src=None):
+    with open(src or KERNEL_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(name):
+def measured_traffic(name, src=None):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+    was taken on the current kernel source (src, default the analysis
+    kernel's)."""
     d = load_json(os.path.join(PROFILES, name))
-    if not d or d.get("kernel_sha") != kernel_sha():
+    if not d or d.get("kernel_sha") != kernel_sha(src):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -295,7 +296,8 @@ def run_batched(args, copy_gbs):
     }
     out.update(lat)
     if "ooo" in set(args.workloads.split(",")):
-        out["ooo"] = ooo_run(bt.contexts, max(x.nodes * x.devices for x in ss), max(args.steps, 3), copy_gbs)
+        out["ooo"] = ooo_run(bt.contexts, max(x.nodes * x.devices for x in ss), max(args.steps, 3), copy_gbs,
+                             "ig_ooo_batched_counters.json")
         out["ooo"]["workload"] = ("engine over the 256 batched graphs, one workgroup each, one launch: 2 lanes "
                                   "per device, 2 host lanes, window 1024, eager assignment")
         log(f"ooo batched: {out['ooo']['instructions_per_s']:.3g} instructions/s, "
@@ -404,7 +406,10 @@ def ooo_algorithmic_bytes(n_instr, n_edges):
     return 84 * n_instr + 28 * n_edges
 
 
-def ooo_run(contexts, devices, steps, copy_gbs):
+OOO_SRC = os.path.join(ROOT, "paper_2503_10516_amd", "csrc", "ig_ooo.hip")
+
+
+def ooo_run(contexts, devices, steps, copy_gbs, counters=None):
     """Time `steps` runs of the engine over the contexts' graphs (one launch
     of the preparation kernels and the engine, HIP events on the stream)."""
     import numpy as np
@@ -433,7 +438,8 @@ def ooo_run(contexts, devices, steps, copy_gbs):
             "makespan_ns_max": max(s["makespan"] for s in summ),
             "eager_fraction": sum(s["eager"] for s in summ) / max(1, n),
             "roofline": {"bound": "hbm", "achieved": ab / sec / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": ab / sec / 1e9 / PEAK_HBM_GBS, "traffic": None,
+                         "frac": ab / sec / 1e9 / PEAK_HBM_GBS,
+                         "traffic": measured_traffic(counters, OOO_SRC) if counters else None,
                          "kernel": "ig_ooo_prep_* + ig_ooo_engine", "algorithmic_bytes": ab,
                          "frac_of_copy": ab / sec / 1e9 / copy_gbs if copy_gbs else None}}
 
@@ -448,7 +454,7 @@ def run_ooo_stencil2d(steps, threads, copy_gbs):
     ctx.record(s)
     ctx.flush()
     assert ctx.sync() == 0
-    out = ooo_run([ctx], s.nodes * s.devices, steps, copy_gbs)
+    out = ooo_run([ctx], s.nodes * s.devices, steps, copy_gbs, "ig_ooo_stencil2d_counters.json")
     gold = load_json(os.path.join(GOLDEN, "stencil2d_full_ooo.json"))
     if gold:
         sim = binding.OooSimulation([ctx], binding.ooo_params(s.nodes * s.devices))
