@@ -402,7 +402,8 @@ def ooo_algorithmic_bytes(n_instr, n_edges):
     """Bytes the engine must move at least: per instruction its result slot
     (32 written), its in-flight record (24 written), its lane class,
     duration and the two offset pairs (28 read); per edge the successor entry
-    (12), the dependency id (4) and the dependency's end and lane (12)."""
+    (4) and the successor's dependency-state record (24: half read, half
+    written)."""
     return 84 * n_instr + 28 * n_edges
 
 
