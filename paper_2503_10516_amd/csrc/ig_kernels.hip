@@ -1571,6 +1571,31 @@ IGD void scan_cells(AmCell* cl, const DAlloc& a, const u32 clo[3], const u32 chi
     }
 }
 
+// The same visit restricted to the grid columns i0 = g (mod G) of the box:
+// the G members of a team each take one residue, so every cell is visited
+// by exactly one member.
+template <class F>
+IGD void scan_cells_cols(AmCell* cl, const DAlloc& a, const u32 clo[3], const u32 chi[3], u32 g, u32 G, F f) {
+    const u32 i0f = clo[0] + (g + G - clo[0] % G) % G;
+    if (i0f >= chi[0]) return;
+    const u32 n0 = (chi[0] - 1 - i0f) / G + 1, n1 = chi[1] - clo[1], n2 = chi[2] - clo[2];
+    const u32 total = n0 * n1 * n2;
+    for (u32 base = 0; base < total; base += CELL_BATCH) {
+        AmCell e[CELL_BATCH];
+        AmCell* ptr[CELL_BATCH];
+#pragma unroll
+        for (u32 q = 0; q < CELL_BATCH; ++q) {
+            const u32 t = base + q < total ? base + q : total - 1;
+            const u32 i2 = t % n2, i1 = (t / n2) % n1, j0 = t / (n1 * n2);
+            ptr[q] = cl + alloc_local(a, i0f + j0 * G, clo[1] + i1, clo[2] + i2);
+            e[q] = am_load(ptr[q]);
+        }
+#pragma unroll
+        for (u32 q = 0; q < CELL_BATCH; ++q)
+            if (base + q < total) f(e[q], ptr[q]);
+    }
+}
+
 IGD void cell_init(AmCell* p, u32 w) {
     p->w = w;
     p->r0 = NONE;
@@ -2294,16 +2319,25 @@ IGN void coherence_emit(DevCtx& c, Shared& sh, u32 copy_first) {
     }
 }
 
+// The copies' readers of source allocations, memory by memory: the threads
+// t with t % n_mem == m form memory m's team, member g taking the grid
+// columns i0 = g (mod G) of every record's region, records in inbox order
+// (a cell's readers are only ever added by its one owner).
 IGN void inbox_drain(DevCtx& c, Shared& sh) {
-    for (u32 m = tid(); m < c.n_mem; m += nt()) {
+    const u32 nm = c.n_mem, t = tid();
+    const bool teams = nt() >= nm;
+    const u32 m0 = teams ? t % nm : t, mstep = teams ? nm : nt();
+    const u32 g = teams ? t / nm : 0, G = teams ? (nt() - m0 + nm - 1) / nm : 1;
+    for (u32 m = m0; m < nm; m += mstep) {
         const u32 lo = c.inbox_off[m], hi = lo + c.inbox_cnt[m];
         for (u32 q = lo; q < hi; ++q) {
             const InboxRec& ib = c.inbox[q];
             const DAlloc& a = c.allocs[ib.alloc];
             const u32 x = ib.reader;
-            scan_cells(am_cells(c, a), a, ib.clo, ib.chi,
-                       [&](const AmCell& e, AmCell* p) { cell_add_reader_at(c, sh, m, p, e, x); });
+            scan_cells_cols(am_cells(c, a), a, ib.clo, ib.chi, g, G,
+                            [&](const AmCell& e, AmCell* p) { cell_add_reader_at(c, sh, m, p, e, x); });
         }
+        if (teams) break;
     }
 }
 
