@@ -390,12 +390,15 @@ struct DevStats {
 };
 
 // What the engine knows of an instruction's dependencies, kept current as
-// they are assigned and complete: how many are not yet assigned, how many
-// are incomplete on lanes outside its class, and of those incomplete on its
-// class's lanes the count, the sum of their lanes and of the squares (all on
-// one lane exactly when count * squares == sum^2).
+// they are assigned and complete: how many are not yet assigned (unasg), how
+// many are incomplete on lanes outside its class (foreign), and of those
+// incomplete on its class's lanes the count (inc), the sum of their lanes
+// (suml) and of the squares (all on one lane exactly when count * squares
+// == sum^2).  Two pairs share a 64-bit word each, so one atomic addition
+// updates both (no field ever leaves [0, 2^32), so no carry crosses halves).
 struct OooCnt {
-    u32 unasg, foreign, inc, suml;
+    u64 uf;     // unasg | foreign << 32
+    u64 is;     // inc | suml << 32
     u64 sumsq;
 };
 // Per instruction while it is in flight: the next instruction on its lane

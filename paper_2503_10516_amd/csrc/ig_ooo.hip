@@ -174,8 +174,8 @@ IGD void ooo_prep_node(const OooGraph& g, const ig_ooo_params& p, u32 x) {
     const u32 k0 = ooo_lower_bound(g.e_to, g.ne, x), k1 = ooo_lower_bound(g.e_to, g.ne, x + 1);
     gmem(g.in_off)[x] = k0;
     auto c = gmem(g.cnt) + x;
-    c->unasg = k1 - k0;
-    c->foreign = c->inc = c->suml = 0;
+    c->uf = k1 - k0;
+    c->is = 0;
     c->sumsq = 0;
     gmem(g.out_off)[x] = 0;
     ig_ooo_slot s;
@@ -262,17 +262,20 @@ IGD void ooo_lanes(const ig_ooo_params& p, u32 cls, u32& lo, u32& hi) {
 // engine's own, which complete at once) or it completed on `lane`.
 IGD void ooo_update(const OooGraph& g, const ig_ooo_params& p, u32 y, u32 lane, bool completed) {
     OooCnt* c = g.cnt + y;
-    if (!completed) atomicAdd(&c->unasg, 0xFFFFFFFFu);  // - 1
-    if (lane == NONE) return;
-    u32 lo, hi;
-    ooo_lanes(p, gmem(g.cls)[y], lo, hi);
-    const u32 d = completed ? 0xFFFFFFFFu : 1u;  // -1 or +1, modulo 2^32
-    if (lane < lo || lane >= hi) {
-        atomicAdd(&c->foreign, d);
+    constexpr u64 HI = 1ull << 32;
+    if (lane == NONE) {
+        if (!completed) atomicAdd(&c->uf, 0ull - 1);  // unasg - 1
         return;
     }
-    atomicAdd(&c->inc, d);
-    atomicAdd(&c->suml, completed ? 0u - lane : lane);
+    u32 lo, hi;
+    ooo_lanes(p, gmem(g.cls)[y], lo, hi);
+    if (lane < lo || lane >= hi) {
+        atomicAdd(&c->uf, completed ? 0ull - HI : HI - 1);  // foreign - 1, or unasg - 1 and foreign + 1
+        return;
+    }
+    if (!completed) atomicAdd(&c->uf, 0ull - 1);
+    const u64 d = 1ull | (u64)lane << 32;  // inc + 1, suml + lane
+    atomicAdd(&c->is, completed ? 0ull - d : d);
     const u64 sq = (u64)lane * lane;
     atomicAdd(&c->sumsq, completed ? 0ull - sq : sq);
 }
@@ -289,9 +292,9 @@ IGD void ooo_eval(const OooGraph& g, OooShared& sh, const ig_ooo_params& p, u32 
     const u32 s = y & (OOO_WR - 1);
     if ((sh.asg[s >> 6] >> (s & 63)) & 1ull) return;
     const OooCnt* c = g.cnt + y;
-    const u32 unasg = ig_load_agent(&c->unasg), foreign = ig_load_agent(&c->foreign);
-    const u32 inc = ig_load_agent(&c->inc), suml = ig_load_agent(&c->suml);
+    const u64 uf = ig_load_agent(&c->uf), is = ig_load_agent(&c->is);
     const u64 sumsq = ig_load_agent(&c->sumsq);
+    const u32 unasg = (u32)uf, foreign = (u32)(uf >> 32), inc = (u32)is, suml = (u32)(is >> 32);
     const u32 cls = gmem(g.cls)[y];
     const u32 o0 = gmem(g.out_off)[y], o1 = gmem(g.out_off)[y + 1];
     const u64 dur = gmem(g.dur)[y];
