@@ -465,6 +465,10 @@ def run_ooo_stencil2d(steps, threads, copy_gbs):
         import hashlib
         out["oracle_equal"] = summ == gold["summary"] and \
             hashlib.sha256(slots.tobytes()).hexdigest() == gold["slots_sha256"]
+        secs = gold["runs"][0]["oracle_seconds"]
+        out["cpu_baseline"] = {"value": out["instructions"] / secs, "unit": "instructions/s", "cores": 1,
+                               "kind": "oracle", "sample": f"the oracle's engine over the same graph, {secs} s on one "
+                                                           "core of the host that wrote tests/golden (stored)"}
     ctx.close()
     out["workload"] = ("engine over the 2-D stencil's graph (16 nodes x 8 devices, 1000 tasks): 2 lanes per "
                        "device, 2 host lanes, window 1024, eager assignment, cost model of binding.ooo_params")
