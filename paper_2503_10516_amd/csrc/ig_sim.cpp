@@ -168,7 +168,7 @@ int launch_ooo(const igd::OooGraph* gs, unsigned n_graphs, uint64_t, uint64_t, c
         for (uint32_t x = 0; x < g.n; ++x) igd::ooo_prep_node(g, *p, x);
         for (uint32_t e = 0; e < g.ne; ++e) igd::ooo_prep_edge(g, e);
     }
-    const unsigned threads = 64;
+    const unsigned threads = 16;  // the engine's logic does not depend on the workgroup size
     for (unsigned b = 0; b < n_graphs; ++b) {
         for (int phase = 0; phase < 2; ++phase) {
             igd::OooShared* sh = new igd::OooShared();
