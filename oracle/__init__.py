@@ -56,7 +56,7 @@ class ContextDesc(ctypes.Structure):
                 ("chunks", ctypes.c_uint32), ("horizon_step", ctypes.c_uint32),
                 ("lookahead", ctypes.c_uint32), ("flush_horizons", ctypes.c_uint32),
                 ("queue_cap", ctypes.c_uint32), ("horizon_mode", ctypes.c_uint32),
-                ("horizon_max_tasks", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+                ("horizon_max_tasks", ctypes.c_uint32), ("staging", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -172,10 +172,10 @@ class OracleContext:
     """One stream analysed by the oracle."""
 
     def __init__(self, nodes, devices, chunks=0, horizon_step=0, lookahead=1,
-                 flush_horizons=0, queue_cap=0, horizon_mode=0, horizon_max_tasks=0):
+                 flush_horizons=0, queue_cap=0, horizon_mode=0, horizon_max_tasks=0, staging=0):
         self.L = lib()
         d = ContextDesc(nodes, devices, chunks, horizon_step, lookahead, flush_horizons, queue_cap, horizon_mode,
-                        horizon_max_tasks, 0)
+                        horizon_max_tasks, staging)
         self.h = ctypes.c_void_p()
         st = self.L.igo_context_create(ctypes.byref(d), ctypes.byref(self.h))
         if st != 0:

@@ -484,7 +484,7 @@ struct Sources {  // incoming edges of one instruction, kinds OR-ed per source
 
 struct igo_context {
     uint32_t nodes, devices, chunks, per_dev, horizon_step, lookahead, flush_horizons, queue_cap;
-    uint32_t horizon_mode = 0, horizon_max_tasks = 0;
+    uint32_t horizon_mode = 0, horizon_max_tasks = 0, staging = 0;
     // task graph (horizon_mode 1): critical-path lengths of the task-level
     // synchronisation point (latest epoch or applied horizon), of the latest
     // epoch, of the generated horizon not yet applied (0: none), the longest
@@ -822,13 +822,32 @@ struct igo_context {
                     const uint32_t src = std::get<2>(g.first);
                     uint8_t flags = 0;
                     if (src_mem >= 2 && node_of_mem(src_mem) != node_of_mem(m)) flags |= IGO_F_INTER_NODE;
+                    // without direct device-to-device copies (staging), a
+                    // copy between devices of one node goes through M1
+                    const bool staged = staging && src_mem >= 2 && !(flags & IGO_F_INTER_NODE);
                     for (const Box& cb : canonical(g.second)) {
-                        const uint32_t ci = emit(IGO_COPY, flags, t.id, (uint32_t)k, b, m, src_mem, dst, src, cb);
-                        std::vector<Access> acc = {{src, cb, IGO_READ}, {dst, cb, IGO_WRITE}};
-                        Sources s;
-                        access_edges(acc, s);
-                        finish(ci, s);
-                        access_apply(ci, acc);
+                        if (staged) {
+                            const uint32_t c1 = emit(IGO_COPY, 0, t.id, (uint32_t)k, b, 1, src_mem, 0, src, cb);
+                            std::vector<Access> a1 = {{src, cb, IGO_READ}};
+                            Sources s1;
+                            access_edges(a1, s1);
+                            finish(c1, s1);
+                            access_apply(c1, a1);
+                            const uint32_t c2 = emit(IGO_COPY, 0, t.id, (uint32_t)k, b, m, 1, dst, 0, cb);
+                            std::vector<Access> a2 = {{dst, cb, IGO_WRITE}};
+                            Sources s2;
+                            s2.add(c1, IGO_DEP_TRUE);
+                            access_edges(a2, s2);
+                            finish(c2, s2);
+                            access_apply(c2, a2);
+                        } else {
+                            const uint32_t ci = emit(IGO_COPY, flags, t.id, (uint32_t)k, b, m, src_mem, dst, src, cb);
+                            std::vector<Access> acc = {{src, cb, IGO_READ}, {dst, cb, IGO_WRITE}};
+                            Sources s;
+                            access_edges(acc, s);
+                            finish(ci, s);
+                            access_apply(ci, acc);
+                        }
                         mask_add(b, cb, m);
                     }
                 }
@@ -1116,6 +1135,7 @@ int32_t igo_context_create(const igo_context_desc* d, igo_context** out) {
     c->queue_cap = d->queue_cap;
     c->horizon_mode = d->horizon_mode;
     c->horizon_max_tasks = d->horizon_max_tasks ? d->horizon_max_tasks : 16 * c->horizon_step;
+    c->staging = d->staging;
     c->allocs.push_back(Alloc{0, 0, 0, Box{{0, 0, 0}, {0, 0, 0}}, false, {}});
     // the initial epoch I0
     c->emit(IGO_EPOCH, 0, NONE, NONE, NONE, NONE16, NONE16, 0, 0, Box{{0, 0, 0}, {0, 0, 0}});

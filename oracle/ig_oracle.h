@@ -105,7 +105,14 @@ typedef struct igo_context_desc {
      * horizon_step), whichever comes first. */
     uint32_t horizon_mode;
     uint32_t horizon_max_tasks;
-    uint32_t pad;
+    /* Sec. 3.3, last paragraph: 1 when devices cannot copy to each other
+     * directly.  A coherence copy between two devices of one node is then
+     * staged through pinned host memory M1 as two copies: device to M1 (it
+     * reads the source allocation) and M1 to device (it writes the
+     * destination allocation and depends on the first); the staging space is
+     * the executor's, outside the graph (allocation id 0 on the M1 side).
+     * Copies between nodes are unchanged. */
+    uint32_t staging;
 } igo_context_desc;
 
 typedef struct igo_instruction {

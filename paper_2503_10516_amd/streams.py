@@ -68,6 +68,7 @@ class Stream:
     queue_cap: int = 0
     horizon_mode: int = 0        # 0: a horizon every horizon_step tasks; 1: from the task graph (Sec. 3.5)
     horizon_max_tasks: int = 0   # mode 1: tasks between horizons at most (0: 16 x horizon_step)
+    staging: int = 0             # 1: device-to-device copies within a node staged through pinned host memory
     cmds: List[tuple] = field(default_factory=list)
     name: str = ""
 
@@ -102,7 +103,7 @@ class Stream:
         return dict(nodes=self.nodes, devices=self.devices, chunks=self.chunks,
                     horizon_step=self.horizon_step, lookahead=self.lookahead,
                     flush_horizons=self.flush_horizons, queue_cap=self.queue_cap,
-                    horizon_mode=self.horizon_mode, horizon_max_tasks=self.horizon_max_tasks)
+                    horizon_mode=self.horizon_mode, horizon_max_tasks=self.horizon_max_tasks, staging=self.staging)
 
 
 def splitmix64(x: int) -> int:
