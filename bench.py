@@ -395,6 +395,47 @@ def run_task_graph_horizons(threads):
 
 
 # ---------------------------------------------------------------------------
+# Host-staged device-to-device copies (Sec. 3.3, last paragraph)
+# ---------------------------------------------------------------------------
+
+def run_staged(steps, threads):
+    """The 2-D stencil with staging on (devices that cannot copy to each
+    other): analysis throughput and the digests against the oracle run
+    here."""
+    import dataclasses
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2503_10516_amd import binding, streams
+    s = dataclasses.replace(streams.stencil_2d(), staging=1, name="stencil2d_staged")
+    ctx = binding.make_context(s, threads=threads)
+    ctx.record(s)
+    times = []
+    for k in range(steps + 1):
+        if k:
+            ctx.rewind()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.flush()
+        assert ctx.sync() == 0
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    st = ctx.stats()
+    ctx.close()
+    t = time.perf_counter()
+    ref = oracle.run_stream(s, fetch=False)["stats"]
+    oracle_s = time.perf_counter() - t
+    rec = st["n_instructions"] + st["n_edges"]
+    sec = float(np.median(times[1:]))
+    return {"workload": "2-D 5-point stencil (4096x4096, 1000 tasks, 16 nodes x 8 devices, 128 chunks) with "
+                        "device-to-device copies within a node staged through pinned host memory",
+            "records": rec, "copies": st["per_kind"][2], "ms_per_analysis": sec * 1e3, "records_per_s": rec / sec,
+            "oracle_equal": all(st[k] == ref[k] for k in DIGEST_KEYS),
+            "cpu_baseline": {"value": rec / oracle_s, "unit": "records/s", "cores": 1, "kind": "oracle",
+                             "sample": "the whole stream, one run"}}
+
+
+# ---------------------------------------------------------------------------
 # Out-of-order engine simulation (Sec. 4.1) over finished graphs
 # ---------------------------------------------------------------------------
 
@@ -504,10 +545,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--threads", type=int, default=256, help="workgroup size of the single-stream objects")
-    ap.add_argument("--workloads", default="stencil2d,nbody,stencil1d,tdag,serving,ooo",
+    ap.add_argument("--workloads", default="stencil2d,nbody,stencil1d,tdag,serving,ooo,staged",
                     help="comma list of objects beside the batched headline: stencil2d, nbody, stencil1d, tdag "
                          "(horizons from the task graph), serving, ooo (the out-of-order engine simulated over "
-                         "the 2-D stencil's and the batched graphs)")
+                         "the 2-D stencil's and the batched graphs), staged (host-staged device copies)")
     ap.add_argument("--batch-threads", type=int, default=0, help="0: autotune")
     ap.add_argument("--batch-window", type=int, default=400, help="commands per launch while sizing")
     ap.add_argument("--serving-rates", default="1e3,1e5")
@@ -591,6 +632,10 @@ def main():
         line["task_graph_horizons"] = run_task_graph_horizons(args.threads)
     if "serving" in work:
         line["serving"] = run_serving(args)
+    if "staged" in work:
+        line["staged"] = run_staged(max(args.steps, 3), args.threads)
+        log(f"staged stencil2d: {line['staged']['records_per_s']:.3g} records/s, oracle equal "
+            f"{line['staged']['oracle_equal']}")
     if "ooo" in work:
         line["ooo"] = {"stencil2d": run_ooo_stencil2d(max(args.steps, 3), args.threads, copy_gbs),
                        "batched": line["batched"].pop("ooo", None)}

@@ -153,6 +153,12 @@ typedef struct ig_context_desc {
                                    task graph: when its critical-path length has grown by horizon_step
                                    since the last horizon or epoch, or horizon_max_tasks tasks came since */
     uint32_t horizon_max_tasks; /* horizon_mode 1: tasks between horizons at most (0: 16 x horizon_step) */
+    uint32_t staging;           /* Sec. 3.3, last paragraph: 1 when devices cannot copy to each other: a
+                                   coherence copy between two devices of one node becomes a copy into
+                                   pinned host memory M1 (reading the source allocation) and one from it
+                                   (writing the destination, depending on the first); the staging space
+                                   is the executor's (allocation 0 on the M1 side).  0: direct copies */
+    uint32_t pad2;
     uint64_t cap_commands;      /* recorded commands (0: 65536) */
     uint64_t cap_instructions;  /* output instructions (0: 1<<20) */
     uint64_t cap_edges;         /* output edges (0: 4 * cap_instructions) */

@@ -66,6 +66,7 @@ class ContextDesc(ctypes.Structure):
                 ("lookahead", ctypes.c_uint32), ("flush_horizons", ctypes.c_uint32),
                 ("queue_cap", ctypes.c_uint32), ("threads", ctypes.c_uint32),
                 ("horizon_mode", ctypes.c_uint32), ("horizon_max_tasks", ctypes.c_uint32),
+                ("staging", ctypes.c_uint32), ("pad2", ctypes.c_uint32),
                 ("cap_commands", ctypes.c_uint64), ("cap_instructions", ctypes.c_uint64),
                 ("cap_edges", ctypes.c_uint64), ("cap_state_words", ctypes.c_uint64),
                 ("cap_unit", ctypes.c_uint64), ("cap_scratch", ctypes.c_uint64),
@@ -282,6 +283,7 @@ def context_desc(L, device, stream=None, **kw):
     d.flush_horizons, d.queue_cap = kw.get("flush_horizons", 0), kw.get("queue_cap", 0)
     d.threads = kw.get("threads", 0)
     d.horizon_mode, d.horizon_max_tasks = kw.get("horizon_mode", 0), kw.get("horizon_max_tasks", 0)
+    d.staging = kw.get("staging", 0)
     d.cap_commands, d.cap_instructions = kw.get("cap_commands", 0), kw.get("cap_instructions", 0)
     d.cap_edges, d.cap_state_words = kw.get("cap_edges", 0), kw.get("cap_state_words", 0)
     d.cap_unit, d.cap_scratch = kw.get("cap_unit", 0), kw.get("cap_scratch", 0)
@@ -310,7 +312,7 @@ class Context:
     def __init__(self, nodes, devices, chunks=0, horizon_step=0, lookahead=1, flush_horizons=0,
                  queue_cap=0, threads=0, lib_path=None, device=None, cap_commands=0,
                  cap_instructions=0, cap_edges=0, cap_state_words=0, cap_unit=0, cap_scratch=0, stream=None,
-                 horizon_mode=0, horizon_max_tasks=0):
+                 horizon_mode=0, horizon_max_tasks=0, staging=0):
         self.L = lib(lib_path)
         if device is None:
             device = "cuda" if lib_path is None else "host"
@@ -318,7 +320,7 @@ class Context:
         d, self.arena, self.torch_stream = context_desc(
             self.L, device, stream, nodes=nodes, devices=devices, chunks=chunks, horizon_step=horizon_step,
             lookahead=lookahead, flush_horizons=flush_horizons, queue_cap=queue_cap, threads=threads,
-            horizon_mode=horizon_mode, horizon_max_tasks=horizon_max_tasks,
+            horizon_mode=horizon_mode, horizon_max_tasks=horizon_max_tasks, staging=staging,
             cap_commands=cap_commands, cap_instructions=cap_instructions, cap_edges=cap_edges,
             cap_state_words=cap_state_words, cap_unit=cap_unit, cap_scratch=cap_scratch)
         self.desc = d

@@ -15,6 +15,7 @@ struct Caps {
     u32 nodes, devices, chunks, per_dev, n_dev, n_mem, mw;
     u32 horizon_step, lookahead, flush_horizons, queue_cap, threads, n_workers;
     u32 horizon_mode, horizon_max_tasks;
+    u32 staging;
     u32 cap_cmds, cap_allocs, cap_queue, cap_heap, cap_rb, cap_unit, cap_scr, cap_src, cap_box;
     u64 cap_instr, cap_edges, cap_binds;
     u64 pack_bytes;
@@ -67,6 +68,8 @@ static bool make_caps(const ig_context_desc* d, Caps& k) {
     if (d->horizon_mode > 1) return false;
     k.horizon_mode = d->horizon_mode;
     k.horizon_max_tasks = d->horizon_max_tasks ? d->horizon_max_tasks : 16 * k.horizon_step;
+    if (d->staging > 1) return false;
+    k.staging = d->staging;
     k.threads = d->threads ? d->threads : 256;
     if (k.threads < 64 || k.threads > MAX_THREADS || (k.threads & 63)) return false;
     k.n_workers = std::min(k.threads, k.n_mem);
@@ -207,6 +210,7 @@ static void fill_config(const Caps& k, DevCtx& h) {
     h.n_workers = k.n_workers;
     h.horizon_mode = k.horizon_mode;
     h.horizon_max_tasks = k.horizon_max_tasks;
+    h.staging = k.staging;
     h.cap_cmds = k.cap_cmds;
     h.cap_allocs = k.cap_allocs;
     h.cap_queue = k.cap_queue;

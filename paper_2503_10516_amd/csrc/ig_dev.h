@@ -249,7 +249,8 @@ struct RdGroup {
 // A coherence copy found in the counting pass.
 struct CopyRec {
     u32 chunk, buffer, src_alloc, dst_alloc;
-    u32 src_mem, dst_mem, pad0, pad1;  // pad0: chunk * IG_MAX_ACCESS + access
+    u32 src_mem, dst_mem, pad0, pad1;  // pad0: chunk * IG_MAX_ACCESS + access; pad1: instruction offset
+                                       // within its device's copies (emission)
     u32 clo[3], chi[3];
 };
 
@@ -294,6 +295,7 @@ struct DevCtx {
     u32 horizon_step, lookahead, flush_horizons, queue_cap;
     u32 threads, n_workers;
     u32 horizon_mode, horizon_max_tasks;
+    u32 staging, pad_staging;  // 1: device-to-device copies within a node staged through M1
     u32 cap_cmds, cap_allocs, cap_queue, cap_heap, cap_rb, cap_unit, cap_scr, cap_src, cap_box;
     u32 pad0;
     u64 cap_instr, cap_edges, cap_binds;

@@ -1852,6 +1852,20 @@ IGD u32 team_size(const DevCtx& c) {
     return g;
 }
 
+// Without direct device-to-device copies (staging), a copy between two
+// devices of one node becomes two instructions, through pinned host memory.
+IGD bool copy_staged(const DevCtx& c, u32 src_mem, u32 dst_mem) {
+    return c.staging && src_mem >= 2 && (src_mem - 2) / c.devices == (dst_mem - 2) / c.devices;
+}
+
+// Copies of the records [off, off + n) that are staged.
+IGD u32 staged_among(const DevCtx& c, u32 off, u32 n) {
+    u32 st = 0;
+    if (c.staging)
+        for (u32 q = off; q < off + n; ++q) st += copy_staged(c, c.copies[q].src_mem, c.copies[q].dst_mem);
+    return st;
+}
+
 IGN void coherence_count(DevCtx& c, Shared& sh) {
     const u32 A = sh.t_nacc, K = c.per_dev;
     const u32 G = team_size(c);
@@ -2088,7 +2102,7 @@ IGN void coherence_count(DevCtx& c, Shared& sh) {
                 for (u32 i = 0; i < n; ++i) atomicOr(&mask[(size_t)gv[i] * c.mw + (m >> 6)], 1ull << (m & 63));
                 c.cons_off[idx] = off;
                 c.cons_cnt[idx] = cnt;
-                total += cnt;
+                total += cnt + staged_among(c, off, cnt);  // instructions
             }
         }
         c.dev_cnt[d] = total;
@@ -2255,6 +2269,8 @@ IGN void coherence_big(DevCtx& c, Shared& sh) {
             if (act && ge > gs) {
                 const DBuf& B = c.bufs[b];
                 emit_groups(c, sh, key2 + gs, val2 + gs, ge - gs, B, k, j, b, dst, m, tm[3] + boff, true);
+                const u32 st = staged_among(c, tm[3] + boff, cnt);  // the second halves of staged copies
+                if (st) atomicAdd(&c.dev_cnt[d], st);
                 u64* mask = W64(c, B.mask_off);
                 for (u32 e = gs; e < ge; ++e) atomicOr(&mask[(size_t)val2[e] * c.mw + (m >> 6)], 1ull << (m & 63));
             }
@@ -2271,12 +2287,17 @@ IGN void coherence_emit(DevCtx& c, Shared& sh, u32 copy_first) {
     for (u32 m = tid(); m < c.n_mem; m += nt()) {
         if (m < 2) continue;
         const u32 d = m - 2;
+        // instruction offsets within the device: a staged copy takes two
         u32 run = 0;
         for (u32 k = d * K; k < (d + 1) * K; ++k)
             for (u32 j = 0; j < A; ++j) {
                 const u32 idx = k * IG_MAX_ACCESS + j;
                 c.cons_x[idx] = run;
-                run += c.cons_cnt[idx];
+                const u32 q0 = c.cons_off[idx], q1 = q0 + c.cons_cnt[idx];
+                for (u32 q = q0; q < q1; ++q) {
+                    c.copies[q].pad1 = run;
+                    run += copy_staged(c, c.copies[q].src_mem, m) ? 2 : 1;
+                }
             }
     }
     bar();
@@ -2292,22 +2313,44 @@ IGN void coherence_emit(DevCtx& c, Shared& sh, u32 copy_first) {
     for (u32 q = q0; q < q1; ++q) {
         const CopyRec& cr = c.copies[q];
         const u32 m = cr.dst_mem, idx = cr.pad0;
-        const u32 x = copy_first + c.dev_base[m - 2] + c.cons_x[idx] + (q - c.cons_off[idx]);
+        const u32 x = copy_first + c.dev_base[m - 2] + cr.pad1;
+        (void)idx;
         const DBuf& B = c.bufs[cr.buffer];
         const DAlloc& sa = c.allocs[cr.src_alloc];
         const DAlloc& da = c.allocs[cr.dst_alloc];
         const i64 lo[3] = {bps(c, B, 0)[cr.clo[0]], bps(c, B, 1)[cr.clo[1]], bps(c, B, 2)[cr.clo[2]]};
         const i64 hi[3] = {bps(c, B, 0)[cr.chi[0]], bps(c, B, 1)[cr.chi[1]], bps(c, B, 2)[cr.chi[2]]};
         const bool inter = cr.src_mem >= 2 && (cr.src_mem - 2) / c.devices != (m - 2) / c.devices;
-        put_instr(c, x, IG_COPY, inter ? IG_F_INTER_NODE : 0, sh.t_id, cr.chunk, cr.buffer, m, cr.src_mem,
-                  cr.dst_alloc, cr.src_alloc, lo, hi);
-        SrcSet s;
-        ss_init(c, s);
-        scan_cells(am_cells(c, sa), sa, cr.clo, cr.chi, [&](const AmCell& e, AmCell*) { cell_read_edge(sh, s, e); });
         AmCell* dcl = am_cells(c, da);
-        scan_cells(dcl, da, cr.clo, cr.chi, [&](const AmCell& e, AmCell*) { cell_write_edge(c, sh, s, e); });
-        stage(c, sh, x, s);
-        scan_cells(dcl, da, cr.clo, cr.chi, [&](const AmCell& e, AmCell* p) { cell_set_writer_at(c, m, p, e, x); });
+        if (copy_staged(c, cr.src_mem, m)) {
+            // device -> M1 (reads the source), then M1 -> device (writes the
+            // destination, after the first)
+            put_instr(c, x, IG_COPY, 0, sh.t_id, cr.chunk, cr.buffer, 1, cr.src_mem, 0, cr.src_alloc, lo, hi);
+            SrcSet s;
+            ss_init(c, s);
+            scan_cells(am_cells(c, sa), sa, cr.clo, cr.chi,
+                       [&](const AmCell& e, AmCell*) { cell_read_edge(sh, s, e); });
+            stage(c, sh, x, s);
+            put_instr(c, x + 1, IG_COPY, 0, sh.t_id, cr.chunk, cr.buffer, m, 1, cr.dst_alloc, 0, lo, hi);
+            SrcSet s2;
+            ss_init(c, s2);
+            ss_add(sh, s2, x, IG_DEP_TRUE);
+            scan_cells(dcl, da, cr.clo, cr.chi, [&](const AmCell& e, AmCell*) { cell_write_edge(c, sh, s2, e); });
+            stage(c, sh, x + 1, s2);
+            scan_cells(dcl, da, cr.clo, cr.chi,
+                       [&](const AmCell& e, AmCell* p) { cell_set_writer_at(c, m, p, e, x + 1); });
+        } else {
+            put_instr(c, x, IG_COPY, inter ? IG_F_INTER_NODE : 0, sh.t_id, cr.chunk, cr.buffer, m, cr.src_mem,
+                      cr.dst_alloc, cr.src_alloc, lo, hi);
+            SrcSet s;
+            ss_init(c, s);
+            scan_cells(am_cells(c, sa), sa, cr.clo, cr.chi,
+                       [&](const AmCell& e, AmCell*) { cell_read_edge(sh, s, e); });
+            scan_cells(dcl, da, cr.clo, cr.chi, [&](const AmCell& e, AmCell*) { cell_write_edge(c, sh, s, e); });
+            stage(c, sh, x, s);
+            scan_cells(dcl, da, cr.clo, cr.chi,
+                       [&](const AmCell& e, AmCell* p) { cell_set_writer_at(c, m, p, e, x); });
+        }
         const u32 slot = atomicAdd(&c.inbox_cur[cr.src_mem], 1u);
         InboxRec& ib = c.inbox[slot];
         ib.alloc = cr.src_alloc;

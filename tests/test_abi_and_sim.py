@@ -380,3 +380,22 @@ def test_sim_ooo_rejects_bad_parameters_and_lanes(sim_lib):
         sim.close()
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("index", range(8))
+def test_sim_staged_copies_equal_oracle(index, sim_lib):
+    """Device-to-device copies staged through pinned host memory (Sec. 3.3,
+    last paragraph): the kernel's pairs, ids and edges equal the oracle's."""
+    import dataclasses
+    from test_oracle_staging import cases
+    picks = [0, 2, 3, 4, 5, 7, 22, 26]
+    s = cases()[picks[index]]
+    s = dataclasses.replace(s, staging=1, name=s.name + "_staged")
+    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=64 if index % 2 else 256), s.name)
+
+
+def test_sim_staged_big_reads(sim_lib):
+    """Staging with large reads scanned by thread teams (the deferred path)."""
+    import dataclasses
+    s = dataclasses.replace(big_read_stream(1), staging=1)
+    assert_same(oracle.run_stream(s), B.run_stream(s, lib_path=sim_lib, threads=256), s.name)

@@ -343,3 +343,36 @@ def test_batched_full_size_streams_with_all_reads():
         for k in DIGESTS + ("per_kind", "per_dep"):
             assert st[k] == rows[i][k], (i, k)
     bt.close()
+
+
+# ---------------------------------------------------------------------------
+# device-to-device copies staged through pinned host memory (Sec. 3.3, last
+# paragraph), against the oracle run here
+# ---------------------------------------------------------------------------
+
+def _staged(s):
+    import dataclasses
+    return dataclasses.replace(s, staging=1, name=s.name + "_staged")
+
+
+@pytest.mark.parametrize("index", range(30))
+def test_staged_copies_equal_oracle(index):
+    from test_oracle_staging import cases
+    s = _staged(cases()[index])
+    print(f"[gpu] staged {s.name}", flush=True)
+    assert_same(oracle.run_stream(s), B.run_stream(s), s.name)
+
+
+@pytest.mark.parametrize("index,threads", [(191, 256), (90, 256), (147, 1024), (138, 64)])
+def test_staged_full_size_batched_streams(index, threads):
+    """Full-size streams of the batched workload (512-1024 chunks over 2-8
+    nodes of 8 devices) with staging, record by record."""
+    s = _staged(S.batched_stream(S.BATCHED_SEED, index, w_all=S.BATCHED_W_ALL, w_slice=S.BATCHED_W_SLICE))
+    print(f"[gpu] staged batched_{index}, {threads} threads", flush=True)
+    assert_same(oracle.run_stream(s), B.run_stream(s, threads=threads), s.name)
+
+
+def test_staged_full_size_stencil2d():
+    s = _staged(S.stencil_2d())
+    print("[gpu] staged stencil2d full", flush=True)
+    assert_same(oracle.run_stream(s), B.run_stream(s), s.name)
