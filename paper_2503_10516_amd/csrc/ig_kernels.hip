@@ -2293,6 +2293,10 @@ IGN void coherence_emit(DevCtx& c, Shared& sh, u32 copy_first) {
             for (u32 j = 0; j < A; ++j) {
                 const u32 idx = k * IG_MAX_ACCESS + j;
                 c.cons_x[idx] = run;
+                if (!c.staging) {
+                    run += c.cons_cnt[idx];
+                    continue;
+                }
                 const u32 q0 = c.cons_off[idx], q1 = q0 + c.cons_cnt[idx];
                 for (u32 q = q0; q < q1; ++q) {
                     c.copies[q].pad1 = run;
@@ -2313,8 +2317,7 @@ IGN void coherence_emit(DevCtx& c, Shared& sh, u32 copy_first) {
     for (u32 q = q0; q < q1; ++q) {
         const CopyRec& cr = c.copies[q];
         const u32 m = cr.dst_mem, idx = cr.pad0;
-        const u32 x = copy_first + c.dev_base[m - 2] + cr.pad1;
-        (void)idx;
+        const u32 x = copy_first + c.dev_base[m - 2] + (c.staging ? cr.pad1 : c.cons_x[idx] + (q - c.cons_off[idx]));
         const DBuf& B = c.bufs[cr.buffer];
         const DAlloc& sa = c.allocs[cr.src_alloc];
         const DAlloc& da = c.allocs[cr.dst_alloc];
