@@ -2279,6 +2279,28 @@ IGN void coherence_big(DevCtx& c, Shared& sh) {
     }
 }
 
+// A staged copy: device -> M1 (reads the source), then M1 -> device (writes
+// the destination, after the first), ids x and x + 1.  Kept out of line so
+// that the direct copies' code keeps its registers.
+IGN void emit_staged_copy(DevCtx& c, Shared& sh, const CopyRec& cr, u32 x, const i64 lo[3], const i64 hi[3]) {
+    const u32 m = cr.dst_mem;
+    const DAlloc& sa = c.allocs[cr.src_alloc];
+    const DAlloc& da = c.allocs[cr.dst_alloc];
+    AmCell* dcl = am_cells(c, da);
+    put_instr(c, x, IG_COPY, 0, sh.t_id, cr.chunk, cr.buffer, 1, cr.src_mem, 0, cr.src_alloc, lo, hi);
+    SrcSet s;
+    ss_init(c, s);
+    scan_cells(am_cells(c, sa), sa, cr.clo, cr.chi, [&](const AmCell& e, AmCell*) { cell_read_edge(sh, s, e); });
+    stage(c, sh, x, s);
+    put_instr(c, x + 1, IG_COPY, 0, sh.t_id, cr.chunk, cr.buffer, m, 1, cr.dst_alloc, 0, lo, hi);
+    SrcSet s2;
+    ss_init(c, s2);
+    ss_add(sh, s2, x, IG_DEP_TRUE);
+    scan_cells(dcl, da, cr.clo, cr.chi, [&](const AmCell& e, AmCell*) { cell_write_edge(c, sh, s2, e); });
+    stage(c, sh, x + 1, s2);
+    scan_cells(dcl, da, cr.clo, cr.chi, [&](const AmCell& e, AmCell* p) { cell_set_writer_at(c, m, p, e, x + 1); });
+}
+
 // Emission pass: ids, records, edges, updates of the destination maps; the
 // reads of source allocations go to their owners' inboxes.
 IGN void coherence_emit(DevCtx& c, Shared& sh, u32 copy_first) {
@@ -2326,22 +2348,7 @@ IGN void coherence_emit(DevCtx& c, Shared& sh, u32 copy_first) {
         const bool inter = cr.src_mem >= 2 && (cr.src_mem - 2) / c.devices != (m - 2) / c.devices;
         AmCell* dcl = am_cells(c, da);
         if (copy_staged(c, cr.src_mem, m)) {
-            // device -> M1 (reads the source), then M1 -> device (writes the
-            // destination, after the first)
-            put_instr(c, x, IG_COPY, 0, sh.t_id, cr.chunk, cr.buffer, 1, cr.src_mem, 0, cr.src_alloc, lo, hi);
-            SrcSet s;
-            ss_init(c, s);
-            scan_cells(am_cells(c, sa), sa, cr.clo, cr.chi,
-                       [&](const AmCell& e, AmCell*) { cell_read_edge(sh, s, e); });
-            stage(c, sh, x, s);
-            put_instr(c, x + 1, IG_COPY, 0, sh.t_id, cr.chunk, cr.buffer, m, 1, cr.dst_alloc, 0, lo, hi);
-            SrcSet s2;
-            ss_init(c, s2);
-            ss_add(sh, s2, x, IG_DEP_TRUE);
-            scan_cells(dcl, da, cr.clo, cr.chi, [&](const AmCell& e, AmCell*) { cell_write_edge(c, sh, s2, e); });
-            stage(c, sh, x + 1, s2);
-            scan_cells(dcl, da, cr.clo, cr.chi,
-                       [&](const AmCell& e, AmCell* p) { cell_set_writer_at(c, m, p, e, x + 1); });
+            emit_staged_copy(c, sh, cr, x, lo, hi);
         } else {
             put_instr(c, x, IG_COPY, inter ? IG_F_INTER_NODE : 0, sh.t_id, cr.chunk, cr.buffer, m, cr.src_mem,
                       cr.dst_alloc, cr.src_alloc, lo, hi);
