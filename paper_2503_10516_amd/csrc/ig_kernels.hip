@@ -53,6 +53,8 @@ struct Shared {
     u64 tick;
     u64 wkey[256 * 16];  // per-worker stale-cell keys of one consumer (small case)
     u32 wval[256 * 16];
+    u32 rbs_head[MAX_THREADS];  // per thread: a private run of free reader blocks (0: none)
+    u16 rbs_mem[MAX_THREADS];   // ... of this memory
 };
 
 IGD u32 tid() { return ig_tid(); }
@@ -230,13 +232,45 @@ IGD void rd_each(const DevCtx& c, u32 head, F f) {
 // block) changed only by compare-and-swap, the tag counting every change, so
 // that threads taking and returning blocks of one memory at once cannot be
 // fooled by a head that was taken and returned in between.
+// A thread takes up to RB_TAKE blocks of a memory's free list with one
+// compare-and-swap and keeps the rest as a private run (rbs_head), used
+// before the shared list is touched again; the run goes back to the free
+// list when the thread needs another memory's blocks and at the end of
+// every compiled command (rb_stash_return).
+constexpr u32 RB_TAKE = 4;
+IGD void rd_clear(DevCtx& c, u32 m, u32* head);
+IGD void rb_stash_return(DevCtx& c, Shared& sh) {
+    u32* h = &sh.rbs_head[tid()];
+    if (*h) rd_clear(c, sh.rbs_mem[tid()], h);
+}
+IGN u32 rb_alloc_slow(DevCtx& c, Shared& sh, u32 m);
 IGD u32 rb_alloc(DevCtx& c, Shared& sh, u32 m) {
+    u32& run = sh.rbs_head[tid()];
+    if (run && sh.rbs_mem[tid()] == m) {
+        const u32 h = run;
+        run = c.rb[h * 8 + 7];
+        return h;
+    }
+    return rb_alloc_slow(c, sh, m);
+}
+// out of line: the shared free list, or fresh blocks
+IGN u32 rb_alloc_slow(DevCtx& c, Shared& sh, u32 m) {
+    u32& run = sh.rbs_head[tid()];
+    rb_stash_return(c, sh);
     u64 old = atomicAdd(&c.rb_free[m], 0ull);
     while ((u32)old) {
         const u32 h = (u32)old;
-        const u64 nw = (((old >> 32) + 1) << 32) | c.rb[h * 8 + 7];
+        u32 last = h;
+        for (u32 k = 1; k < RB_TAKE && c.rb[last * 8 + 7]; ++k) last = c.rb[last * 8 + 7];
+        const u64 nw = (((old >> 32) + 1) << 32) | c.rb[last * 8 + 7];
         const u64 seen = atomicCAS(&c.rb_free[m], old, nw);
-        if (seen == old) return h;
+        if (seen == old) {
+            // the tag did not change, so h .. last were still linked: they are ours
+            c.rb[last * 8 + 7] = 0;
+            run = last == h ? 0u : c.rb[h * 8 + 7];
+            sh.rbs_mem[tid()] = (u16)m;
+            return h;
+        }
         old = seen;
     }
     u32 i = atomicAdd(&sh.s.rb_top, 1u);
@@ -1236,6 +1270,7 @@ IGD void unit_begin(DevCtx& c, Shared& sh) {
 }
 
 IGN void unit_end(DevCtx& c, Shared& sh) {
+    rb_stash_return(c, sh);
     if (failed(sh)) return;
     const u32 n = sh.unit_n;
     // per-instruction edge counts -> output offsets
@@ -3596,6 +3631,7 @@ IGN void analyse(DevCtx& c, Shared& sh, u32 window) {
         sh.s = c.s;
         sh.tick = ig_clock();
     }
+    sh.rbs_head[tid()] = 0;
     bar();
     const u32 first = sh.s.cmd_next;
     const u32 end = window && c.cmd_end - first > window ? first + window : c.cmd_end;
@@ -3647,6 +3683,7 @@ IGN void analyse(DevCtx& c, Shared& sh, u32 window) {
         if (tid() == 0 && !sh.s.error) sh.s.cmd_next = ci + 1;
         bar();
     }
+    rb_stash_return(c, sh);
     bar();
     if (tid() == 0) {
         sh.s.done_tasks = done_prefix(c, sh.s);
