@@ -524,7 +524,7 @@ typedef struct ig_ooo_summary {
 typedef struct ig_ooo ig_ooo;
 /* A simulation handle over the graphs of n contexts (synchronises each
  * context's stream to read its record counts).  Allocates device memory for
- * the per-instruction results (32 bytes each) and a workspace of 68 bytes
+ * the per-instruction results (32 bytes each) and a workspace of 64 bytes
  * per instruction and 4 per edge.  Errors: IG_E_INVALID (parameters out of range, a context
  * with an analysis error, more than 2^31 - 1 instructions), IG_E_DEVICE. */
 ig_status ig_ooo_create(ig_context* const* ctxs, size_t n, const ig_ooo_params* p, ig_ooo** out);

@@ -1070,7 +1070,7 @@ ig_status ig_ooo_create(ig_context* const* ctxs, size_t n, const ig_ooo_params* 
         const Scalars& sc = ctxs[i]->s;
         if (sc.error || sc.n_instr > 0x7FFFFFFFull || sc.n_edges > 0xFFFFFFFFull) return IG_E_INVALID;
         const u64 m = sc.n_instr, e = sc.n_edges;
-        bytes += al256(m * sizeof(ig_ooo_slot)) + 2 * al256((m + 1) * 4) + al256(e * 4) + al256(m * sizeof(OooRec)) +
+        bytes += al256(m * sizeof(ig_ooo_slot)) + al256((m + 1) * 4) + al256(e * 4) + al256(m * sizeof(OooRec)) +
                  al256(m * sizeof(OooCnt)) + al256(m * 4) + al256(m * 8);
     }
     ig_ooo* o = new ig_ooo();
@@ -1105,7 +1105,6 @@ ig_status ig_ooo_create(ig_context* const* ctxs, size_t n, const ig_ooo_params* 
         g.sum = o->dsum + i;
         g.status = o->dstatus + i;
         g.out = (ig_ooo_slot*)take((u64)g.n * sizeof(ig_ooo_slot));
-        g.in_off = (u32*)take(((u64)g.n + 1) * 4);
         g.out_off = (u32*)take(((u64)g.n + 1) * 4);
         g.out_adj = (u32*)take((u64)g.ne * 4);
         g.cnt = (OooCnt*)take((u64)g.n * sizeof(OooCnt));

@@ -426,7 +426,6 @@ struct OooGraph {
     ig_ooo_summary* sum;  // [1]
     i32* status;          // [1]
     // workspace
-    u32* in_off;   // [n + 1] first edge of each target
     u32* out_off;  // [n + 1] successor list offsets (counts before the scan)
     u32* out_adj;  // [ne] successors
     OooCnt* cnt;   // [n] dependency state

@@ -4,20 +4,24 @@
 //
 // One workgroup simulates one graph, reading the context's records where
 // they lie in HBM.  Preparation runs grid-wide: per instruction its lane
-// class and duration, the start of its dependency list (edges are stored
-// sorted by target, so that is a lower bound), and the successor lists
-// (counted, scanned, filled).  The engine itself is sequential in time but
-// parallel inside each round:
+// class, duration and number of dependencies (edges are stored sorted by
+// target, so the dependency list starts at a lower bound), and the
+// successor lists (counted, scanned, filled).  The engine itself is
+// sequential in time but parallel inside each round:
 //   * the window's state lives in LDS as bitmaps over a ring of
 //     IG_OOO_MAX_WINDOW slots (slot = id mod ring): "assignable at the start
 //     of the next round" and "assigned";
+//   * each instruction's dependency state (how many are unassigned, how many
+//     incomplete on foreign lanes, and the count and lane sums of those on
+//     its own class's lanes) is kept current in HBM by atomic additions when
+//     a dependency is assigned or completes;
 //   * after a round (or a completion), only the successors of what changed
-//     and the ids that entered the window are evaluated, by all threads in
-//     parallel -- an instruction none of whose dependencies changed cannot
+//     and the ids that entered the window are evaluated, one thread per
+//     successor -- an instruction none of whose dependencies changed cannot
 //     have become assignable, so this equals re-evaluating the whole window;
-//   * one thread then assigns the round's instructions in id order (lane
-//     choice and FIFO order are sequential by definition), walking the ring
-//     bitmap word by word;
+//   * the round's instructions are assigned in id order by one thread per
+//     lane class (classes share no lane), walking the ring bitmap's
+//     non-empty words;
 //   * each lane is a FIFO of in-flight instructions (a linked list through
 //     the workspace); with positive durations their ends strictly increase
 //     along a lane, so the next completion is the minimum over lane heads
@@ -172,7 +176,6 @@ IGD void ooo_prep_node(const OooGraph& g, const ig_ooo_params& p, u32 x) {
     gmem(g.cls)[x] = cls;
     gmem(g.dur)[x] = dur;
     const u32 k0 = ooo_lower_bound(g.e_to, g.ne, x), k1 = ooo_lower_bound(g.e_to, g.ne, x + 1);
-    gmem(g.in_off)[x] = k0;
     auto c = gmem(g.cnt) + x;
     c->uf = k1 - k0;
     c->is = 0;
@@ -189,7 +192,6 @@ IGD void ooo_prep_node(const OooGraph& g, const ig_ooo_params& p, u32 x) {
 
 // The closing entries of the two offset arrays (one thread per graph).
 IGD void ooo_prep_tail(const OooGraph& g) {
-    gmem(g.in_off)[g.n] = g.ne;
     gmem(g.out_off)[g.n] = 0;
 }
 
