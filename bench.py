@@ -383,10 +383,16 @@ def run_task_graph_horizons(threads):
             dt = time.perf_counter() - t
             st = ctx.stats()
             ctx.close()
+            # the oracle beside it: its time is this object's CPU baseline,
+            # and its digests are compared with the device's
+            t = time.perf_counter()
             ref = oracle.run_stream(s, fetch=False)["stats"]
-            row[f"mode{mode}"] = {"gpu_ms": dt * 1e3, "horizons": st["per_kind"][5],
-                                  "records": st["n_instructions"] + st["n_edges"],
-                                  "oracle_equal": all(st[k] == ref[k] for k in DIGEST_KEYS)}
+            oracle_s = time.perf_counter() - t
+            rec = st["n_instructions"] + st["n_edges"]
+            row[f"mode{mode}"] = {"gpu_ms": dt * 1e3, "horizons": st["per_kind"][5], "records": rec,
+                                  "oracle_equal": all(st[k] == ref[k] for k in DIGEST_KEYS),
+                                  "cpu_baseline": {"value": rec / oracle_s, "unit": "records/s", "cores": 1,
+                                                   "kind": "oracle", "sample": "the whole stream, one run"}}
         s.horizon_mode = 0
         out.append(row)
         log(f"task-graph horizons {name}: {row['mode0']['horizons']} -> {row['mode1']['horizons']} horizons, "
