@@ -171,3 +171,46 @@ def test_ooo_full_size_stencil2d_against_oracle_golden():
             assert hashlib.sha256(slots.tobytes()).hexdigest() == run["slots_sha256"], run["params"]
     finally:
         ctx.close()
+
+
+def _analysed(s):
+    """A context holding s's graph (capacities grown on overflow)."""
+    from paper_2503_10516_amd import batch as BT
+    caps = B.estimate_caps(s)
+    caps.update(BT.fixed_caps(s))
+    for _ in range(4):
+        ctx = B.make_context(s, **caps)
+        ctx.record(s)
+        ctx.flush()
+        st = ctx.sync()
+        if st == B.IG_E_CAPACITY:
+            ctx.close()
+            for k in ("cap_instructions", "cap_edges", "cap_state_words", "cap_unit", "cap_scratch"):
+                caps[k] = int(caps[k] * 3)
+            continue
+        assert st == 0, (s.name, st)
+        return ctx
+    raise AssertionError(f"{s.name}: capacities")
+
+
+@pytest.mark.parametrize("index", [191, 90, 147])
+def test_ooo_full_size_batched_graphs_properties(index):
+    """The engine over full-size graphs of the batched workload (512-1024
+    chunks, 3-4e5 instructions, millions of edges), three at once in one
+    launch as in the benchmark: every property of a correct run holds."""
+    s = S.batched_stream(S.BATCHED_SEED, index, w_all=S.BATCHED_W_ALL, w_slice=S.BATCHED_W_SLICE)
+    print(f"[gpu] ooo batched_{index} full size", flush=True)
+    ctx = _analysed(s)
+    other = _analysed(S.nbody_example())
+    try:
+        out = ctx.fetch_all()
+        devs = s.nodes * s.devices
+        p = B.ooo_params(devs)
+        sim = B.OooSimulation([other, ctx], p)
+        sim.run()
+        slots, summ = sim.fetch(1)
+        sim.close()
+        check_engine_properties(out["instructions"], out["edges"], slots, summ, p, devs * p.lanes_per_device)
+    finally:
+        ctx.close()
+        other.close()
